@@ -1,0 +1,224 @@
+"""FP64 CPU oracle for the Sinkhorn divergence (Feydy et al., arXiv 2107.02010).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.  It shares no
+code with the HIP library.  The arithmetic lives in ``oracle.c`` (plain C,
+double precision); this module compiles it with gcc on first use and marshals
+numpy arrays to it.  FP32 inputs are widened to FP64 exactly.
+
+Notation follows Section 2 and the Algorithm of the paper:
+``f = b^{beta->alpha}``, ``g = a^{alpha->beta}``, ``p = a^{alpha<->alpha}``,
+``q = b^{beta<->beta}``; ``eps = sigma**2``, ``rho = reach**2``; ``reach=None``
+(or inf, or <= 0) is the balanced problem.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_D = ctypes.c_double
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_P = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, IEEE semantics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            lib.oracle_softmin.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _P]
+            lib.oracle_softmin.restype = None
+            lib.oracle_diameter.argtypes = [_I64, _I64, _I, _P, _P]
+            lib.oracle_diameter.restype = _D
+            lib.oracle_schedule.argtypes = [_D, _D, _D, _P, _I]
+            lib.oracle_schedule.restype = _I
+            lib.oracle_sinkhorn.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _D, _D,
+                                            _I, _D, _I, _I, _I, _P, _P, _P, _P, _P]
+            lib.oracle_sinkhorn.restype = _I
+            lib.oracle_divergence.argtypes = [_I64, _I64, _P, _P, _P, _P, _P, _P, _D, _D]
+            lib.oracle_divergence.restype = _D
+            lib.oracle_ot_dual.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _D]
+            lib.oracle_ot_dual.restype = _D
+            lib.oracle_ot_primal.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _D]
+            lib.oracle_ot_primal.restype = _D
+            lib.oracle_marginals.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _P, _P]
+            lib.oracle_marginals.restype = None
+            lib.oracle_plan_apply.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _P,
+                                              _I, _I, _P]
+            lib.oracle_plan_apply.restype = None
+            lib.oracle_grad_x.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _P, _D, _P]
+            lib.oracle_grad_x.restype = None
+            _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_P)
+
+
+def _pts(x):
+    x = _f64(x)
+    if x.ndim == 1:
+        x = x.reshape(-1, 1)
+    return x
+
+
+def _reach(reach):
+    if reach is None or not (reach > 0) or math.isinf(reach):
+        return 0.0
+    return float(reach)
+
+
+def softmin(rows, cols, w, h, eps, lam=1.0):
+    """out_i = -lam*eps*log sum_j w_j exp((h_j - C(rows_i, cols_j))/eps)  (Algorithm, tilde updates)."""
+    r, c = _pts(rows), _pts(cols)
+    w, h = _f64(w), _f64(h)
+    out = np.empty(r.shape[0])
+    _load().oracle_softmin(r.shape[0], c.shape[0], r.shape[1], _ptr(r), _ptr(c), _ptr(w),
+                           _ptr(h), float(eps), float(lam), _ptr(out))
+    return out
+
+
+def diameter(x, y):
+    """Joint bounding-box diagonal, the reading of the Algorithm's diameter heuristic."""
+    x, y = _pts(x), _pts(y)
+    return _load().oracle_diameter(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(y))
+
+
+def schedule(diam, blur, scaling):
+    """The list [d, d q, ..., blur] of the Algorithm's loop header."""
+    lib = _load()
+    n = lib.oracle_schedule(float(diam), float(blur), float(scaling), None, 0)
+    out = np.empty(n)
+    lib.oracle_schedule(float(diam), float(blur), float(scaling), _ptr(out), n)
+    return out
+
+
+def sinkhorn(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0, tol=0.0,
+             max_iters=0, check_every=1, init=None):
+    """Symmetric averaged Sinkhorn loop with eps-scaling (Algorithm).
+
+    Returns dict(f, g, p, q, iters, n_scales, marginal_err, diameter, eps, converged).
+    """
+    x, y = _pts(x), _pts(y)
+    a, b = _f64(a), _f64(b)
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    if init is None:
+        f, g, p, q = np.zeros(n), np.zeros(m), np.zeros(n), np.zeros(m)
+        flag = 0
+    else:
+        f, g, p, q = (_f64(v).copy() for v in init)
+        flag = 1
+    info = np.zeros(6)
+    _load().oracle_sinkhorn(n, m, d, _ptr(x), _ptr(a), _ptr(y), _ptr(b), float(blur),
+                            _reach(reach), float(scaling), float(diam or 0.0), int(extra_iters),
+                            float(tol), int(max_iters), int(check_every), flag, _ptr(f), _ptr(g),
+                            _ptr(p), _ptr(q), _ptr(info))
+    return dict(f=f, g=g, p=p, q=q, iters=int(info[0]), n_scales=int(info[1]),
+                marginal_err=float(info[2]), diameter=float(info[3]), eps=float(info[4]),
+                converged=bool(info[5]))
+
+
+def divergence(a, b, f, g, p, q, blur, reach=None):
+    """S_{eps,rho} in the dual form of eq. (6) at eps = blur**2."""
+    a, b, f, g, p, q = (_f64(v) for v in (a, b, f, g, p, q))
+    return _load().oracle_divergence(a.size, b.size, _ptr(a), _ptr(b), _ptr(f), _ptr(g), _ptr(p),
+                                     _ptr(q), float(blur), _reach(reach))
+
+
+def ot_dual(x, a, y, b, f, g, eps, reach=None):
+    """Dual objective of eq. (3) at (f, g)."""
+    x, y = _pts(x), _pts(y)
+    a, b, f, g = (_f64(v) for v in (a, b, f, g))
+    return _load().oracle_ot_dual(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
+                                  _ptr(b), _ptr(f), _ptr(g), float(eps), _reach(reach))
+
+
+def ot_primal(x, a, y, b, f, g, eps, reach=None):
+    """Primal objective of eq. (2) at the plan of eq. (4) built from (f, g)."""
+    x, y = _pts(x), _pts(y)
+    a, b, f, g = (_f64(v) for v in (a, b, f, g))
+    return _load().oracle_ot_primal(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
+                                    _ptr(b), _ptr(f), _ptr(g), float(eps), _reach(reach))
+
+
+def divergence_eq5(x, a, y, b, f, g, p, q, blur, reach=None):
+    """S by eq. (5), each OT term by its dual objective eq. (3) at the given potentials."""
+    eps = float(blur) ** 2
+    ab = ot_dual(x, a, y, b, f, g, eps, reach)
+    aa = ot_dual(x, a, x, a, p, p, eps, reach)
+    bb = ot_dual(y, b, y, b, q, q, eps, reach)
+    ma, mb = float(np.sum(_f64(a))), float(np.sum(_f64(b)))
+    return ab - 0.5 * aa - 0.5 * bb + 0.5 * eps * (ma - mb) ** 2
+
+
+def marginals(x, a, y, b, f, g, eps):
+    """Row and column sums of the plan of eq. (4)."""
+    x, y = _pts(x), _pts(y)
+    a, b, f, g = (_f64(v) for v in (a, b, f, g))
+    row, col = np.empty(x.shape[0]), np.empty(y.shape[0])
+    _load().oracle_marginals(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
+                             _ptr(b), _ptr(f), _ptr(g), float(eps), _ptr(row), _ptr(col))
+    return row, col
+
+
+def plan_apply(x, a, y, b, f, g, eps, V, divide_by_a=False):
+    """(pi V)_i of eq. (4); with divide_by_a the soft labels of eq. (7)."""
+    x, y = _pts(x), _pts(y)
+    a, b, f, g = (_f64(v) for v in (a, b, f, g))
+    V = _f64(V)
+    if V.ndim == 1:
+        V = V.reshape(-1, 1)
+    out = np.empty((x.shape[0], V.shape[1]))
+    _load().oracle_plan_apply(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
+                              _ptr(b), _ptr(f), _ptr(g), float(eps), _ptr(V), V.shape[1],
+                              int(bool(divide_by_a)), _ptr(out))
+    return out
+
+
+def grad_x(x, a, y, b, f, g, p, eps):
+    """Gradient of S with respect to x from the dual vectors (envelope theorem on eq. (3))."""
+    x, y = _pts(x), _pts(y)
+    a, b, f, g, p = (_f64(v) for v in (a, b, f, g, p))
+    out = np.empty_like(x)
+    _load().oracle_grad_x(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y), _ptr(b),
+                          _ptr(f), _ptr(g), _ptr(p), float(eps), _ptr(out))
+    return out
+
+
+def sinkhorn_divergence(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0,
+                        tol=0.0, max_iters=0, check_every=1):
+    """Run the loop and return (S by eq. (6), the loop's result dict)."""
+    r = sinkhorn(x, a, y, b, blur, reach, scaling, diam, extra_iters, tol, max_iters, check_every)
+    S = divergence(a, b, r["f"], r["g"], r["p"], r["q"], blur, reach)
+    return S, r

@@ -1,0 +1,125 @@
+"""Seeded synthetic inputs shared by the oracle checks, the GPU tests and the benchmark.
+
+This module only draws point clouds and weights (numpy PCG64 generators); it
+holds none of the optimal-transport arithmetic.  Every generator is a pure
+function of its arguments, returns FP32 arrays, and stands in for data the
+paper uses but that is not available here (HCP tractograms, the fibre atlas and
+the IFOF track-density maps).
+
+* ``blobs``       isotropic Gaussian blobs in the unit cube (3-D clouds).
+* ``fibers``      tractogram-like clouds: fibres along random cubic Bezier
+                  spines with per-fibre control-point jitter, resampled to P
+                  points at equal arc length and flattened to P*3 features
+                  scaled by 1/sqrt(P) (the paper's fibre encoding, Section 2).
+* ``uniform_weights``  1/N weights.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_weights(n: int) -> np.ndarray:
+    return np.full(n, 1.0 / n, dtype=np.float32) if n > 0 else np.zeros(0, np.float32)
+
+
+def blobs(n: int, seed: int, n_blobs: int = 3, sigma: float = 0.1, d: int = 3,
+          lo: float = 0.2, hi: float = 0.8) -> np.ndarray:
+    """n points, split as evenly as possible over ``n_blobs`` isotropic Gaussians.
+
+    Centres ~ U[lo, hi]^d and offsets ~ N(0, sigma^2) both come from ``seed``;
+    the first ``n % n_blobs`` blobs take one extra point.  No clipping.
+    """
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(lo, hi, size=(n_blobs, d))
+    sizes = [n // n_blobs + (1 if k < n % n_blobs else 0) for k in range(n_blobs)]
+    parts = [centres[k] + sigma * rng.standard_normal((sizes[k], d)) for k in range(n_blobs)]
+    out = np.concatenate(parts, axis=0) if n > 0 else np.zeros((0, d))
+    return out.astype(np.float32)
+
+
+def _bezier(ctrl: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Cubic Bezier curves. ctrl: (F, 4, 3); t: (T,) -> (F, T, 3)."""
+    s = 1.0 - t
+    basis = np.stack([s ** 3, 3 * s * s * t, 3 * s * t * t, t ** 3], axis=1)  # (T, 4)
+    return np.einsum("tk,fkc->ftc", basis, ctrl)
+
+
+def _resample_equal_arclength(poly: np.ndarray, P: int) -> np.ndarray:
+    """Resample polylines (F, T, 3) to P points equally spaced in arc length (both ends kept)."""
+    F, T, _ = poly.shape
+    seg = np.linalg.norm(np.diff(poly, axis=1), axis=2)
+    cum = np.concatenate([np.zeros((F, 1)), np.cumsum(seg, axis=1)], axis=1)  # (F, T)
+    targets = cum[:, -1:] * np.linspace(0.0, 1.0, P)[None, :]  # (F, P)
+    # searchsorted per row: count of cum <= target, minus one
+    idx = (cum[:, None, :] <= targets[:, :, None]).sum(axis=2) - 1
+    idx = np.clip(idx, 0, T - 2)
+    rows = np.arange(F)[:, None]
+    c0, c1 = cum[rows, idx], cum[rows, idx + 1]
+    den = np.where(c1 > c0, c1 - c0, 1.0)
+    w = np.where(c1 > c0, (targets - c0) / den, 0.0)
+    p0, p1 = poly[rows, idx], poly[rows, idx + 1]
+    return p0 + w[..., None] * (p1 - p0)
+
+
+def fibers(n: int, n_bundles: int, spine_seed: int, seed: int, points: int = 20,
+           box: float = 150.0, jitter: float = 2.0, samples: int = 256,
+           chunk: int = 8192) -> np.ndarray:
+    """Tractogram-like cloud of n fibres, returned as (n, 3*points) FP32.
+
+    * ``n_bundles`` spines, each a cubic Bezier curve with 4 control points
+      ~ U[0, box]^3 drawn from ``spine_seed`` (shared by the two clouds of a pair).
+    * Fibre k of a bundle jitters every control point by N(0, jitter^2) per
+      coordinate, drawn from ``seed``.
+    * Bundle sizes are n // n_bundles, the first n % n_bundles bundles taking one
+      more fibre; fibres are stored bundle after bundle.
+    * Each fibre is sampled at ``samples`` uniform curve parameters, then
+      resampled to ``points`` points at equal arc length, flattened point-major
+      (p0x, p0y, p0z, p1x, ...) and scaled by 1/sqrt(points), so that the
+      Euclidean distance of two feature vectors is the RMS point distance.
+    """
+    srng = np.random.default_rng(spine_seed)
+    spines = srng.uniform(0.0, box, size=(n_bundles, 4, 3))
+    rng = np.random.default_rng(seed)
+    sizes = np.array([n // n_bundles + (1 if k < n % n_bundles else 0) for k in range(n_bundles)])
+    bundle_of = np.repeat(np.arange(n_bundles), sizes)
+    t = np.linspace(0.0, 1.0, samples)
+    out = np.empty((n, 3 * points), dtype=np.float32)
+    scale = 1.0 / np.sqrt(points)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        ctrl = spines[bundle_of[s:e]] + jitter * rng.standard_normal((e - s, 4, 3))
+        poly = _bezier(ctrl, t)
+        res = _resample_equal_arclength(poly, points)
+        out[s:e] = (res.reshape(e - s, 3 * points) * scale).astype(np.float32)
+    return out
+
+
+def fiber_pair(n: int, n_bundles: int, seed: int, points: int = 20):
+    """Two clouds of the same anatomy: shared spines (seed), fibre jitter seeds seed+1 and seed+2."""
+    x = fibers(n, n_bundles, spine_seed=seed, seed=seed + 1, points=points)
+    y = fibers(n, n_bundles, spine_seed=seed, seed=seed + 2, points=points)
+    return x, uniform_weights(n), y, uniform_weights(n)
+
+
+def blob_pair(n: int, seed: int, d: int = 3):
+    """Config-1 style pair: x from ``seed``, y from ``seed + 1`` (centres redrawn)."""
+    x = blobs(n, seed, d=d)
+    y = blobs(n, seed + 1, d=d)
+    return x, uniform_weights(n), y, uniform_weights(n)
+
+
+def random_weights(n: int, seed: int, total: float = 1.0, zero_frac: float = 0.0) -> np.ndarray:
+    """Positive random weights summing to ``total``; a fraction may be set to exactly zero."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.2, 1.0, size=n)
+    if zero_frac > 0 and n > 1:
+        k = int(zero_frac * n)
+        w[rng.choice(n, size=k, replace=False)] = 0.0
+    if w.sum() <= 0:
+        w[0] = 1.0
+    return (w / w.sum() * total).astype(np.float32)
+
+
+def random_cloud(n: int, d: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (scale * rng.standard_normal((n, d))).astype(np.float32)
