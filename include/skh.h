@@ -1,0 +1,137 @@
+/*
+ * skh — symmetric, debiased, multiscale Sinkhorn divergence on MI355X (gfx950).
+ *
+ * C ABI of libskh.so.  The operations follow the problem statement of Feydy,
+ * Roussillon, Trouve, Gori, "Fast and Scalable Optimal Transport for Brain
+ * Tractograms" (MICCAI 2019, arXiv 2107.02010), Section 2:
+ *
+ *   alpha = sum_i a_i delta_{x_i},  beta = sum_j b_j delta_{y_j},  x, y in R^D,
+ *   cost C(x, y) = |x - y|^2 / 2  (p = 2),
+ *   eps = sigma^2, rho = reach^2, lambda = 1 / (1 + eps / rho).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Point arrays are row-major FP32, n x d (point i at x[i*d .. i*d+d-1]);
+ *    weights and potentials are FP32 vectors.  Every array pointer is a DEVICE
+ *    pointer on the context's device, owned by the caller.  Inputs are never
+ *    written; outputs are written in the caller's point order.
+ *  - 1 <= d <= SKH_MAX_DIM.  n >= 1, m >= 1.
+ *  - All work is enqueued on the context's stream (skh_set_stream).  Calls
+ *    that return host values (S, statistics) synchronise that stream before
+ *    returning; the others return without synchronising.
+ *  - The context owns a workspace that grows on demand and is freed by
+ *    skh_destroy.  One context must not be used by two host threads at once.
+ *  - Return codes: SKH_OK (0); SKH_NOT_CONVERGED (1): outputs are valid but
+ *    the tolerance was not met; negative values are errors, with a message
+ *    from skh_last_error.  On an error no output is guaranteed.
+ *  - balanced problem: reach <= 0 or reach = +inf.
+ */
+#ifndef SKH_H
+#define SKH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKH_MAX_DIM 63
+
+enum {
+    SKH_OK = 0,
+    SKH_NOT_CONVERGED = 1,
+    SKH_EINVAL = -1,     /* bad argument: NULL, sizes, d, blur, scaling, negative or NaN weight */
+    SKH_EHIP = -2,       /* HIP runtime error */
+    SKH_ENOMEM = -3,     /* device allocation failed */
+    SKH_ENONFINITE = -4, /* non-finite coordinate, or non-finite result */
+};
+
+/* precision of the x.y contraction inside the softmin; the log-sum-exp is FP32
+ * in both modes. */
+enum { SKH_FP32 = 0, SKH_BF16_SPLIT = 1 };
+
+typedef struct skh_ctx skh_ctx;
+
+/* Solver parameters (the Algorithm's parameter lines and the two run modes). */
+typedef struct skh_params {
+    double blur;         /* finest scale sigma; eps = blur^2.  > 0 */
+    double reach;        /* rho = reach^2; <= 0 or +inf: balanced */
+    double scaling;      /* ratio q of consecutive scales, in (0, 1); the paper's default is 0.9 */
+    double diameter;     /* largest scale; <= 0: diagonal of the joint bounding box of x and y */
+    double tol;          /* > 0: converged mode, iterate at blur until the marginal error <= tol */
+    int32_t extra_iters; /* iterations at sigma = blur after the scale list (>= 0) */
+    int32_t max_iters;   /* converged mode: at most this many iterations after the list */
+    int32_t check_every; /* converged mode: marginal-error check period (>= 1) */
+    int32_t precision;   /* SKH_FP32 or SKH_BF16_SPLIT */
+    int32_t init;        /* nonzero: f, g, p, q hold starting values (warm start) */
+    int32_t timing;      /* nonzero: time every softmin launch with HIP events (skh_stats) */
+    int32_t reserved[6]; /* must be zero */
+} skh_params;
+
+/* Run statistics. */
+typedef struct skh_stats {
+    int32_t iters;       /* iterations run (each = four softmins + averaging) */
+    int32_t n_scales;    /* length of the scale list */
+    int32_t converged;   /* converged mode: tolerance met */
+    int32_t checks;      /* number of marginal-error checks (each one host sync) */
+    int32_t softmin_launches; /* softmin kernel launches (one per iteration) */
+    int32_t reserved_i[3];
+    double diameter;     /* largest scale used */
+    double eps;          /* eps of the last iteration */
+    double marginal_err; /* last measured relative L1 marginal error (max of the four problems) */
+    double pairs;        /* point pairs evaluated by the softmin kernels */
+    double ms_total;     /* wall time of the call, ms (host clock, inputs resident) */
+    double ms_softmin;   /* params.timing: summed device time of the softmin launches, ms */
+    double reserved[2];
+} skh_stats;
+
+/* Fills *p with blur = 0.05, reach = +inf (balanced), scaling = 0.9,
+ * diameter = 0 (auto), tol = 0 (schedule mode), extra_iters = 0,
+ * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0. */
+void skh_params_default(skh_params *p);
+
+/* Creates a context on HIP device `device` bound to stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns SKH_OK or SKH_EHIP. */
+int skh_create(skh_ctx **out, int device, void *hip_stream);
+void skh_destroy(skh_ctx *ctx);
+/* Rebinds the context to another stream of the same device. */
+int skh_set_stream(skh_ctx *ctx, void *hip_stream);
+/* Message of the last error on this context (ctx may be NULL: last create error). */
+const char *skh_last_error(const skh_ctx *ctx);
+
+/*
+ * One softmin, the reduction behind each of the four updates of the
+ * Algorithm (the tilde lines), on arbitrary inputs:
+ *
+ *   out_i = -lam * eps * log sum_j w_j exp((h_j - C(x_i, y_j)) / eps),  i < n.
+ *
+ * x: n x d rows, y: m x d columns, w: m weights (>= 0; zero weights drop
+ * out), h: m potential values.  eps > 0, 0 < lam <= 1.  A row with no
+ * positive weight gets +inf.  precision: SKH_FP32 or SKH_BF16_SPLIT.
+ * Errors: SKH_EINVAL for bad sizes/arguments, SKH_EHIP.
+ */
+int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
+                const float *w, const float *h, double eps, double lam, int32_t precision,
+                float *out);
+
+/*
+ * Symmetric, debiased Sinkhorn divergence S_{eps,rho}(alpha, beta), eq. (5),
+ * evaluated through its dual form eq. (6) after the averaged symmetric loop
+ * with eps-scaling (Algorithm).  Outputs (all nullable):
+ *   S_out (host): the divergence, summed in FP64 on the device;
+ *   f (n): b^{beta->alpha}, g (m): a^{alpha->beta},
+ *   p (n): a^{alpha<->alpha}, q (m): b^{beta<->beta}  (device, FP32).
+ * When params->init is nonzero, f, g, p, q must be given and hold the
+ * starting values.  Returns SKH_OK, SKH_NOT_CONVERGED (converged mode only),
+ * or an error.  Weights must be >= 0 and not all zero; coordinates finite.
+ */
+int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_t n,
+                            const float *y, const float *b, int64_t m, int32_t d,
+                            const skh_params *params, double *S_out, float *f, float *g, float *p,
+                            float *q, skh_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKH_H */

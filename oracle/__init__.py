@@ -49,6 +49,8 @@ def _load():
         if _lib is None:
             build(force=False)
             lib = ctypes.CDLL(_LIB)
+            lib.oracle_num_threads.argtypes = []
+            lib.oracle_num_threads.restype = _I
             lib.oracle_softmin.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _P]
             lib.oracle_softmin.restype = None
             lib.oracle_diameter.argtypes = [_I64, _I64, _I, _P, _P]
@@ -97,6 +99,11 @@ def _reach(reach):
     if reach is None or not (reach > 0) or math.isinf(reach):
         return 0.0
     return float(reach)
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops run on."""
+    return int(_load().oracle_num_threads())
 
 
 def softmin(rows, cols, w, h, eps, lam=1.0):

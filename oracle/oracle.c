@@ -44,7 +44,20 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define OR_INF (1.0 / 0.0)
+
+/* Number of threads the OpenMP loops below use (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static int is_balanced(double reach) { return !(reach > 0.0) || isinf(reach); }
 

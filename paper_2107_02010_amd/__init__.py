@@ -1,0 +1,139 @@
+"""MI355X-native symmetric, debiased, multiscale Sinkhorn divergence (Feydy et al., arXiv 2107.02010).
+
+Python face of libskh (HIP kernels for gfx950 behind the C ABI of
+``include/skh.h``).  PyTorch is used for device memory and streams only:
+every arithmetic step runs in the library.
+
+    import paper_2107_02010_amd as skh
+    S = skh.sinkhorn_divergence(x, a, y, b, blur=1.0, reach=None, scaling=0.9)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT  # noqa: F401
+
+__all__ = ["softmin", "sinkhorn_divergence", "SkhError", "library_path"]
+
+library_path = _lib.LIB_PATH
+_PREC = {"fp32": _lib.SKH_FP32, "bf16x3": _lib.SKH_BF16_SPLIT, "bf16_split": _lib.SKH_BF16_SPLIT}
+
+
+class _Ctx:
+    """One library context per device; rebound to torch's current stream on each call."""
+
+    _ctxs: dict = {}
+    _lock = threading.Lock()
+
+    @classmethod
+    def get(cls, device: torch.device):
+        idx = device.index if device.index is not None else torch.cuda.current_device()
+        with cls._lock:
+            h = cls._ctxs.get(idx)
+            if h is None:
+                lib = _lib.load()
+                h = ctypes.c_void_p()
+                _lib.check(lib.skh_create(ctypes.byref(h), idx, None))
+                cls._ctxs[idx] = h
+        stream = torch.cuda.current_stream(idx).cuda_stream
+        _lib.check(_lib.load().skh_set_stream(h, ctypes.c_void_p(stream)), h)
+        return h
+
+
+def _as_points(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() == 1:
+        t = t.unsqueeze(1)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be (n, d)")
+    return t.to(torch.float32).contiguous()
+
+
+def _as_vec(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    t = t.to(torch.float32).reshape(-1).contiguous()
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def softmin(x, y, w, h, eps: float, lam: float = 1.0, precision: str = "fp32") -> torch.Tensor:
+    """out_i = -lam*eps*log sum_j w_j exp((h_j - |x_i - y_j|^2/2)/eps), on the GPU.
+
+    The reduction behind the four updates of the Algorithm; x (n, d), y (m, d), w, h (m,).
+    """
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same dimension")
+    w = _as_vec(w, y.shape[0], "w", y.device)
+    h = _as_vec(h, y.shape[0], "h", y.device)
+    out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    ctx = _Ctx.get(x.device)
+    rc = _lib.load().skh_softmin(ctx, _ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1], _ptr(w),
+                                 _ptr(h), float(eps), float(lam), _PREC[precision], _ptr(out))
+    _lib.check(rc, ctx)
+    return out
+
+
+def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: float = 0.9,
+                        diameter=None, extra_iters: int = 0, tol: float = 0.0,
+                        max_iters: int = 1000, check_every: int = 5, precision: str = "fp32",
+                        init=None, potentials: bool = False, timing: bool = False):
+    """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
+
+    x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
+    tol > 0 selects converged mode (iterate at blur until the marginal error <= tol).
+    init: optional (f, g, p, q) starting potentials.  With potentials=True returns
+    (S, dict(f=..., g=..., p=..., q=...), stats dict), else S (a Python float).
+    timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
+    """
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same dimension")
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    a = _as_vec(a, n, "a", x.device)
+    b = _as_vec(b, m, "b", x.device)
+    P = _lib.default_params()
+    P.blur = float(blur)
+    P.reach = math.inf if reach is None else float(reach)
+    P.scaling = float(scaling)
+    P.diameter = 0.0 if diameter is None else float(diameter)
+    P.tol = float(tol)
+    P.extra_iters = int(extra_iters)
+    P.max_iters = int(max_iters)
+    P.check_every = int(check_every)
+    P.precision = _PREC[precision]
+    P.timing = 1 if timing else 0
+    dev = x.device
+    if init is not None:
+        f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in
+                      zip(init, (n, m, n, m), ("f", "g", "p", "q")))
+        P.init = 1
+    else:
+        f = torch.empty(n, dtype=torch.float32, device=dev)
+        g = torch.empty(m, dtype=torch.float32, device=dev)
+        p = torch.empty(n, dtype=torch.float32, device=dev)
+        q = torch.empty(m, dtype=torch.float32, device=dev)
+    S = ctypes.c_double()
+    st = _lib.SkhStats()
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_sinkhorn_divergence(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d,
+                                             ctypes.byref(P), ctypes.byref(S), _ptr(f), _ptr(g),
+                                             _ptr(p), _ptr(q), ctypes.byref(st))
+    _lib.check(rc, ctx, allow_not_converged=True)
+    if potentials:
+        return S.value, dict(f=f, g=g, p=p, q=q), st.as_dict()
+    return S.value

@@ -1,0 +1,101 @@
+"""ctypes binding of libskh.so (include/skh.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+torch tensors to device pointers and the current torch stream to a hipStream_t.
+It raises when the library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskh.so")
+
+SKH_OK = 0
+SKH_NOT_CONVERGED = 1
+SKH_EINVAL = -1
+SKH_EHIP = -2
+SKH_ENOMEM = -3
+SKH_ENONFINITE = -4
+SKH_FP32 = 0
+SKH_BF16_SPLIT = 1
+SKH_MAX_DIM = 63
+
+_c_i32, _c_i64, _c_d, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class SkhParams(ctypes.Structure):
+    _fields_ = [
+        ("blur", _c_d), ("reach", _c_d), ("scaling", _c_d), ("diameter", _c_d), ("tol", _c_d),
+        ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
+        ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("reserved", _c_i32 * 6),
+    ]
+
+
+class SkhStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", _c_i32), ("n_scales", _c_i32), ("converged", _c_i32), ("checks", _c_i32),
+        ("softmin_launches", _c_i32), ("reserved_i", _c_i32 * 3),
+        ("diameter", _c_d), ("eps", _c_d), ("marginal_err", _c_d), ("pairs", _c_d),
+        ("ms_total", _c_d), ("ms_softmin", _c_d), ("reserved", _c_d * 2),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class SkhError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"skh error {code}: {msg}")
+        self.code = code
+
+
+# name -> (restype, argtypes); every entry point declared in include/skh.h
+SIGNATURES = {
+    "skh_params_default": (None, [ctypes.POINTER(SkhParams)]),
+    "skh_create": (_c_i32, [ctypes.POINTER(_c_vp), _c_i32, _c_vp]),
+    "skh_destroy": (None, [_c_vp]),
+    "skh_set_stream": (_c_i32, [_c_vp, _c_vp]),
+    "skh_last_error": (ctypes.c_char_p, [_c_vp]),
+    "skh_softmin": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _c_d, _c_d,
+                             _c_i32, _c_vp]),
+    "skh_sinkhorn_divergence": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32,
+                                         ctypes.POINTER(SkhParams), ctypes.POINTER(_c_d), _c_vp,
+                                         _c_vp, _c_vp, _c_vp, ctypes.POINTER(SkhStats)]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load() -> ctypes.CDLL:
+    """Loads libskh.so from the package directory (built by ``paper_2107_02010_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    f"{LIB_PATH} is missing: build it with `python -m paper_2107_02010_amd.build` "
+                    "(or __graft_entry__.build()); there is no non-HIP fallback")
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def check(rc: int, ctx=None, allow_not_converged: bool = False) -> int:
+    if rc == SKH_OK or (allow_not_converged and rc == SKH_NOT_CONVERGED):
+        return rc
+    msg = load().skh_last_error(ctx)
+    raise SkhError(rc, msg.decode() if msg else "")
+
+
+def default_params() -> SkhParams:
+    p = SkhParams()
+    load().skh_params_default(ctypes.byref(p))
+    return p

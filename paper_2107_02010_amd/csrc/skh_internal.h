@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP kernels and the host driver of libskh.
+// Not part of the public C ABI (include/skh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace skh {
+
+// Packed point layout in HBM: one row of KP floats per point (KP = 4, 8, 16,
+// 32 or 64, the smallest with d + 1 <= KP).  Slots [0, d) hold the coordinates
+// minus a common centre (the cost is translation invariant), slot d is
+// reserved for the augmented term of the softmin contraction, the rest is 0.
+int packed_width(int d);
+
+constexpr int kRowsPerBlock = 128;  // 4 waves x 32 rows
+constexpr int kColsPerTile = 128;   // columns staged to LDS per step
+constexpr int kMaxJobs = 4;
+
+// One softmin reduction over a row set and a column set (one "instance").
+//   L2_i = log2 sum_j 2^{ k * <x_i, y_j> + u_j }    (k = log2(e) / eps)
+// written as (max, sum) partials per column chunk: part[chunk * n_rows + i].
+struct SoftminJob {
+    const float *rows;  // n_rows x KP packed (FP32 path) or bf16 hi/lo planes (split path)
+    const float *cols;  // n_cols x KP packed
+    const float *u;     // n_cols log2-domain column offsets; -inf = no mass
+    float2 *part;       // n_chunks x n_rows
+    int n_rows, n_cols;
+    int row_tiles;      // ceil(n_rows / kRowsPerBlock)
+    int n_chunks;       // column chunks
+    int chunk_cols;     // columns per chunk (multiple of kColsPerTile)
+    int wg_begin;       // first workgroup of this job in the launch
+};
+
+struct SoftminBatch {
+    SoftminJob job[kMaxJobs];
+    int n_jobs;
+    int d;         // coordinates per point; slot d carries the augmented term
+    float kscale;  // log2(e) / eps
+    int pad;
+};
+
+// Builds chunking for a batch of jobs so that the launch holds enough
+// workgroups to fill the device; returns the total workgroup count.
+int plan_softmin_batch(SoftminBatch &b, int target_wgs);
+
+hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
+                          hipStream_t s);
+
+// Bounding box and validation of one cloud.
+//   plo/phi: nb x 64 partial min/max, pmass: nb FP64 partial weight sums,
+//   pbad: nb counts of (non-finite coordinate) + 2^20 * (negative/NaN weight).
+int bbox_blocks(int64_t n);
+hipError_t launch_bbox_partial(const float *x, const float *w, int64_t n, int d, float *plo,
+                               float *phi, double *pmass, int *pbad, hipStream_t s);
+// Reduces the partials of up to two clouds into out: [lo[64], hi[64]] floats,
+// mass[2] doubles, bad[2] ints.
+hipError_t launch_bbox_final(const float *plo, const float *phi, const double *pmass,
+                             const int *pbad, int nb0, int nb1, int d, float *lohi, double *mass,
+                             int *bad, hipStream_t s);
+
+// Packs a cloud: P[i] = x_i - centre (computed in FP64, rounded once), zero
+// padded to KP; hn[i] = |P_i|^2 / 2; lw[i] = log w_i (-inf for w_i = 0).
+hipError_t launch_pack(const float *x, const float *w, int64_t n, int d, int kp,
+                       const float *centre, float *P, float *hn, float *lw, hipStream_t s);
+
+// u_j = log2(e) * (lw_j + (h_j - hn_j) / eps)  (h may be NULL: zero potential).
+hipError_t launch_col_offsets(const float *lw, const float *h, const float *hn, int64_t n,
+                              double eps, float *u, hipStream_t s);
+
+// Merges the chunk partials of one softmin into
+//   out_i = lam * (hn_i - eps * ln2 * L2_i)      (+inf when the row has no mass).
+hipError_t launch_softmin_finish(const float2 *part, int n_chunks, int64_t n, const float *hn,
+                                 double eps, double lam, float *out, hipStream_t s);
+
+// One cloud's side of an iteration: merges the partials of its two softmins
+// (self problem -> s, cross problem -> c), optionally accumulates the
+// marginal-error sums, averages, and writes the next column offsets.
+struct FinishSide {
+    const float2 *part_self;  // partials of the self problem (p~ or q~)
+    const float2 *part_cross; // partials of the cross problem (f~ or g~)
+    int chunks_self, chunks_cross;
+    int64_t n;
+    const float *hn, *lw, *w;
+    float *pot_self, *pot_cross;  // p, f (cloud x) or q, g (cloud y): read, then averaged
+    float *u_self, *u_cross;      // next column offsets for the problems that read this cloud
+};
+// acc: per-block FP64 partials, 4 doubles per block per side:
+// [|r-t| cross, t cross, |r-t| self, t self].
+int finish_blocks(int64_t n);
+hipError_t launch_iteration_finish(const FinishSide &sx, const FinishSide &sy, double eps,
+                                   double lam, double rho, int balanced, double eps_next,
+                                   int check, double *acc, hipStream_t s);
+
+// Sums W doubles over nb blocks of partials (row-major nb x W) in a fixed
+// order into out[W].
+hipError_t launch_sum_partials(const double *part, int nb, int W, double *out, hipStream_t s);
+
+// Per-block FP64 partials of eq. (6): the a-side and b-side terms.
+hipError_t launch_divergence_terms(const float *a, const float *f, const float *p, int64_t n,
+                                   const float *b, const float *g, const float *q, int64_t m,
+                                   double rho, int balanced, double *part, int *nb_out,
+                                   hipStream_t s);
+
+}  // namespace skh

@@ -1,0 +1,190 @@
+// Tiled log-sum-exp softmin on MFMA for gfx950.
+//
+// For a row point x_i and column points y_j (both already centred, FP32) the
+// softmin of the Algorithm's four updates is
+//
+//   -eps log sum_j w_j exp((h_j - C(x_i, y_j)) / eps),   C = |x - y|^2 / 2,
+//
+// and with C(x, y) = |x|^2/2 + |y|^2/2 - <x, y> it becomes
+//
+//   = |x_i|^2/2 - eps ln2 * log2 sum_j 2^{s_ij},
+//   s_ij = k <x_i, y_j> + u_j,  k = log2(e)/eps,  u_j = log2(e) (log w_j + (h_j - |y_j|^2/2)/eps).
+//
+// The kernel computes L2_i = log2 sum_j 2^{s_ij} for a block of rows and a
+// chunk of columns, with an online maximum so that nothing but the running
+// (max, sum) pair per row is kept: O(n + m) memory (Section 2, the
+// linear-memory remark on eqs. (3)-(4)).
+//
+// Contraction on the matrix cores: v_mfma_f32_32x32x2f32 computes a 32 x 32
+// block D[j][i] += Y[j][k] X[k][i] with the column tile Y as operand A (read
+// from LDS) and the row block X as operand B (held in VGPRs for the whole
+// column sweep).  The column offset u_j rides along as one more coordinate:
+// row slot d holds 1.0, column slot d holds u_j, so the MFMA result is s_ij
+// itself.  Output lanes index rows (i = lane % 32) and the 16 accumulator
+// registers index columns, so each lane folds its 16 values into its own
+// running (max, sum) with no cross-lane traffic; the two lane halves that
+// share a row are merged once at the end.
+//
+// Zero weights and the ragged column tail both enter as u_j = -inf, which the
+// contraction turns into s_ij = -inf and the exponential into 0.
+#include "skh_internal.h"
+
+namespace skh {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+static __device__ __forceinline__ float ninf() { return -__builtin_huge_valf(); }
+
+static __device__ __forceinline__ float fast_exp2(float x) {
+    return __builtin_amdgcn_exp2f(x);  // v_exp_f32; inputs below -126 flush toward 0
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
+    constexpr int H = KP / 2;      // k-steps per 32x32 block; lane half h holds dims [h*H, h*H+H)
+    constexpr int STRIDE = KP + 4; // LDS row stride (floats)
+    constexpr int V4 = KP / 4;     // float4 per packed point
+    __shared__ __attribute__((aligned(16))) float tile[kColsPerTile * STRIDE];
+
+    const int wg = blockIdx.x;
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < kMaxJobs; ++t)
+        if (t < B.n_jobs && wg >= B.job[t].wg_begin) q = t;
+    const float *__restrict__ rows = B.job[q].rows;
+    const float *__restrict__ cols = B.job[q].cols;
+    const float *__restrict__ u = B.job[q].u;
+    float2 *__restrict__ part = B.job[q].part;
+    const int n_rows = B.job[q].n_rows, n_cols = B.job[q].n_cols;
+    const int row_tiles = B.job[q].row_tiles, chunk_cols = B.job[q].chunk_cols;
+    const int local = wg - B.job[q].wg_begin;
+    const int rt = local % row_tiles, chunk = local / row_tiles;
+    const int d = B.d;
+    const float kscale = B.kscale;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, li = lane & 31;
+    const int i = rt * kRowsPerBlock + wave * 32 + li;
+    const int ic = i < n_rows ? i : n_rows - 1;
+
+    // Row operand: x_i scaled by k, slot d = 1.
+    float xr[H];
+    {
+        const float *rp = rows + (size_t)ic * KP + h * H;
+        if constexpr (H % 4 == 0) {
+#pragma unroll
+            for (int s = 0; s < H; s += 4) {
+                float4 v = *reinterpret_cast<const float4 *>(rp + s);
+                xr[s] = v.x;
+                xr[s + 1] = v.y;
+                xr[s + 2] = v.z;
+                xr[s + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < H; ++s) xr[s] = rp[s];
+        }
+#pragma unroll
+        for (int s = 0; s < H; ++s) xr[s] = (h * H + s == d) ? 1.0f : xr[s] * kscale;
+    }
+
+    const int c_begin = chunk * chunk_cols;
+    const int c_end = min(n_cols, c_begin + chunk_cols);
+    float m = ninf(), acc_sum = 0.0f;
+
+    for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
+        __syncthreads();
+        for (int e = tid; e < kColsPerTile * V4; e += 256) {
+            const int c = e / V4, v = e - c * V4;
+            const int j = j0 + c;
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < c_end) val = *reinterpret_cast<const float4 *>(cols + (size_t)j * KP + v * 4);
+            if (v == (d >> 2)) {
+                const float uu = j < c_end ? u[j] : ninf();
+                const int r = d & 3;
+                val.x = r == 0 ? uu : val.x;
+                val.y = r == 1 ? uu : val.y;
+                val.z = r == 2 ? uu : val.z;
+                val.w = r == 3 ? uu : val.w;
+            }
+            *reinterpret_cast<float4 *>(&tile[c * STRIDE + v * 4]) = val;
+        }
+        __syncthreads();
+        const int nvalid = c_end - j0;
+        const int nblk = min(kColsPerTile / 32, (nvalid + 31) >> 5);
+        for (int jb = 0; jb < nblk; ++jb) {
+            v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                        0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float *tp = &tile[(jb * 32 + li) * STRIDE + h * H];
+#pragma unroll
+            for (int s = 0; s < H; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[s], xr[s], acc, 0, 0, 0);
+            float tmax = acc[0];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
+            const float mn = fmaxf(m, tmax);
+            if (mn > ninf()) {
+                float sblk = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) sblk += fast_exp2(acc[r] - mn);
+                acc_sum = acc_sum * fast_exp2(m - mn) + sblk;
+                m = mn;
+            }
+        }
+    }
+
+    // Merge the two lane halves that hold the same row.
+    const float m2 = __shfl_xor(m, 32, 64);
+    const float s2 = __shfl_xor(acc_sum, 32, 64);
+    const float M = fmaxf(m, m2);
+    float S = 0.0f;
+    if (M > ninf()) S = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
+    if (h == 0 && i < n_rows) part[(size_t)chunk * n_rows + i] = make_float2(M, S);
+}
+
+int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
+    int row_tiles_total = 0;
+    for (int q = 0; q < b.n_jobs; ++q) {
+        SoftminJob &J = b.job[q];
+        J.row_tiles = (J.n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
+        row_tiles_total += J.row_tiles;
+    }
+    int want_chunks = row_tiles_total > 0 ? (target_wgs + row_tiles_total - 1) / row_tiles_total : 1;
+    if (want_chunks < 1) want_chunks = 1;
+    int total = 0;
+    for (int q = 0; q < b.n_jobs; ++q) {
+        SoftminJob &J = b.job[q];
+        int tiles = (J.n_cols + kColsPerTile - 1) / kColsPerTile;
+        int tiles_per_chunk = (tiles + want_chunks - 1) / want_chunks;
+        if (tiles_per_chunk < 1) tiles_per_chunk = 1;
+        J.chunk_cols = tiles_per_chunk * kColsPerTile;
+        J.n_chunks = (J.n_cols + J.chunk_cols - 1) / J.chunk_cols;
+        if (J.n_chunks < 1) J.n_chunks = 1;
+        J.wg_begin = total;
+        total += J.row_tiles * J.n_chunks;
+    }
+    return total;
+}
+
+hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
+                          hipStream_t s) {
+    (void)precision;
+    dim3 grid(total_wgs), block(256);
+    switch (kp) {
+    case 4: hipLaunchKernelGGL(k_softmin_f32<4>, grid, block, 0, s, b); break;
+    case 8: hipLaunchKernelGGL(k_softmin_f32<8>, grid, block, 0, s, b); break;
+    case 16: hipLaunchKernelGGL(k_softmin_f32<16>, grid, block, 0, s, b); break;
+    case 32: hipLaunchKernelGGL(k_softmin_f32<32>, grid, block, 0, s, b); break;
+    case 64: hipLaunchKernelGGL(k_softmin_f32<64>, grid, block, 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int packed_width(int d) {
+    int kp = 4;
+    while (kp < d + 1) kp *= 2;
+    return kp;
+}
+
+}  // namespace skh

@@ -1,0 +1,130 @@
+"""GPU parity of the full symmetric Sinkhorn loop and of eq. (6) against the FP64 oracle.
+
+Both sides run the same schedule (same diameter reading, same scale list, same
+number of iterations) on the same FP32 inputs.  The FP32 path must match the
+oracle's S to 1e-5 relative; potentials are compared after fixing the
+balanced gauge (f + c, g - c) and within an FP32-propagation tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import cuda, host, note
+
+pytestmark = pytest.mark.gpu
+
+S_RTOL_FP32 = 1e-5
+
+
+def _run(x, a, y, b, blur, reach, scaling, extra=0, **kw):
+    import paper_2107_02010_amd as skh
+    note(f"divergence n={len(x)} m={len(y)} d={x.shape[1]} blur={blur} reach={reach} "
+         f"q={scaling} extra={extra} {kw}")
+    S, pot, st = skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), blur=blur,
+                                         reach=reach, scaling=scaling, extra_iters=extra,
+                                         potentials=True, **kw)
+    return S, {k: host(v) for k, v in pot.items()}, st
+
+
+def _compare(x, a, y, b, blur, reach, scaling, extra=0, pot_atol=None):
+    S, pot, st = _run(x, a, y, b, blur, reach, scaling, extra)
+    Sr, r = oracle.sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling, extra_iters=extra)
+    assert st["iters"] == r["iters"] and st["n_scales"] == r["n_scales"]
+    assert st["diameter"] == pytest.approx(r["diameter"], rel=1e-12)
+    assert S == pytest.approx(Sr, rel=S_RTOL_FP32), (S, Sr)
+    # potentials: compare after removing the mean (gauge), scale-aware tolerance
+    if pot_atol is None:
+        pot_atol = 1e-4 * max(blur ** 2, np.abs(r["f"]).max())
+    for k in ("f", "g", "p", "q"):
+        dg = pot[k] - r[k]
+        dg -= dg.mean() if reach is None else 0.0
+        assert np.max(np.abs(dg)) <= pot_atol, (k, np.max(np.abs(dg)), pot_atol)
+    return S, Sr, st
+
+
+def test_blob_config_full_size_balanced():
+    # 3 isotropic blobs, n = m = 2000 in R^3, blur 0.01, scaling 0.5, no multiscale.
+    x, a, y, b = synth.blob_pair(2000, seed=0)
+    _compare(x, a, y, b, blur=0.01, reach=None, scaling=0.5)
+    _compare(x, a, y, b, blur=0.01, reach=None, scaling=0.5, extra=20)
+
+
+def test_blob_unbalanced_unequal_masses():
+    x, a, y, b = synth.blob_pair(1500, seed=2)
+    b = synth.random_weights(1500, 3, total=1.3, zero_frac=0.05)
+    _compare(x, a, y, b, blur=0.02, reach=0.3, scaling=0.5, extra=5)
+
+
+def test_fiber_downscaled_balanced_fp32():
+    # the 60-D fibre generator at n = m = 3000 (20 bundles), blur 1 mm
+    x, a, y, b = synth.fiber_pair(3000, 20, seed=7)
+    _compare(x, a, y, b, blur=1.0, reach=None, scaling=0.8)
+
+
+def test_fiber_downscaled_unbalanced_fp32():
+    x, a, y, b = synth.fiber_pair(2500, 20, seed=9)
+    _compare(x, a, y, b, blur=1.0, reach=20.0, scaling=0.8, extra=3)
+
+
+@pytest.mark.parametrize("n,m,d", [(1, 1, 3), (1, 37, 2), (130, 1, 5), (257, 129, 1), (5, 300, 60)])
+def test_edge_sizes(n, m, d):
+    rng = np.random.default_rng(n + m + d)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    y = (rng.standard_normal((m, d)) + 0.5).astype(np.float32)
+    a = synth.random_weights(n, 1)
+    b = synth.random_weights(m, 2)
+    _compare(x, a, y, b, blur=0.1 * math.sqrt(d), reach=None, scaling=0.6, extra=2)
+    _compare(x, a, y, b, blur=0.1 * math.sqrt(d), reach=1.0, scaling=0.6, extra=2)
+
+
+def test_converged_mode_meets_tolerance():
+    x, a, y, b = synth.blob_pair(1000, seed=12)
+    S, pot, st = _run(x, a, y, b, 0.05, None, 0.5, tol=1e-4, max_iters=3000, check_every=2)
+    assert st["converged"] == 1 and st["marginal_err"] <= 1e-4
+    Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 0.05, None, scaling=0.5, tol=1e-4,
+                                       max_iters=3000, check_every=2)
+    assert S == pytest.approx(Sr, rel=1e-4)
+
+
+def test_bitwise_reproducible():
+    x, a, y, b = synth.blob_pair(1000, seed=13)
+    S1, p1, _ = _run(x, a, y, b, 0.02, 0.5, 0.5, extra=3)
+    S2, p2, _ = _run(x, a, y, b, 0.02, 0.5, 0.5, extra=3)
+    assert S1 == S2
+    for k in p1:
+        assert np.array_equal(p1[k], p2[k])
+
+
+def test_self_divergence_zero_and_symmetry():
+    x, a, y, b = synth.blob_pair(800, seed=14)
+    S, _, _ = _run(x, a, x, a, 0.02, None, 0.5)
+    assert abs(S) < 1e-6
+    S1, _, _ = _run(x, a, y, b, 0.02, None, 0.5)
+    S2, _, _ = _run(y, b, x, a, 0.02, None, 0.5)
+    assert S1 == pytest.approx(S2, rel=1e-6)
+
+
+def test_invalid_arguments():
+    import paper_2107_02010_amd as skh
+    x, a, y, b = synth.blob_pair(50, seed=15)
+    bad = a.copy()
+    bad[3] = -1.0
+    note("invalid arguments")
+    with pytest.raises(skh.SkhError) as e:
+        skh.sinkhorn_divergence(cuda(x), cuda(bad), cuda(y), cuda(b), blur=0.1)
+    assert e.value.code == -1
+    xn = x.copy()
+    xn[2, 1] = np.nan
+    with pytest.raises(skh.SkhError) as e:
+        skh.sinkhorn_divergence(cuda(xn), cuda(a), cuda(y), cuda(b), blur=0.1)
+    assert e.value.code == -4
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), blur=-1.0)
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), blur=0.1, scaling=1.5)
+    big = np.zeros((10, 64), np.float32)
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(cuda(big), cuda(a[:10] * 5), cuda(big), cuda(a[:10] * 5), blur=0.1)
