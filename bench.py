@@ -156,7 +156,7 @@ def main() -> int:
                      "traffic": traffic,
                      "flop_per_pair": FLOP_PER_PAIR[args.precision],
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-                     "kernel": "k_softmin_f32<64>"},
+                     "kernel": "k_softmin_f32<64>" if args.precision == "fp32" else "k_softmin_bf16<64>"},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a row sample", file=sys.stderr, flush=True)

@@ -131,6 +131,25 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
                             const skh_params *params, double *S_out, float *f, float *g, float *p,
                             float *q, skh_stats *stats);
 
+/*
+ * K-means coarse scale of one cloud (coarse-to-fine strategy, Section 2: a
+ * K-means subsampling of the points for the first, coarse iterations).
+ * Lloyd iterations from k evenly strided points (point floor(c n / k) for
+ * centre c); a point joins the nearest centre, ties to the lowest index; a
+ * centre becomes the w-weighted mean of its members (FP64 sums), an empty or
+ * massless cluster keeps its centre.  After `iters` updates the points are
+ * assigned once more and the centres set to the weighted means of those final
+ * clusters.  w may be NULL (unit weights); 1 <= k <= min(n, 4096); iters >= 0.
+ * Outputs (device, each nullable):
+ *   centres (k x d, caller's coordinates), masses (k, sum of member weights),
+ *   labels (n), perm (n: cluster-sorted position -> point index, stable in
+ *   point order within a cluster), offsets (k + 1: cluster c occupies
+ *   perm[offsets[c] .. offsets[c+1])).
+ */
+int skh_kmeans(skh_ctx *ctx, const float *x, const float *w, int64_t n, int32_t d, int32_t k,
+               int32_t iters, float *centres, float *masses, int32_t *labels, int32_t *perm,
+               int32_t *offsets);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT  # noqa: F401
 
-__all__ = ["softmin", "sinkhorn_divergence", "SkhError", "library_path"]
+__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "SkhError", "library_path"]
 
 library_path = _lib.LIB_PATH
 _PREC = {"fp32": _lib.SKH_FP32, "bf16x3": _lib.SKH_BF16_SPLIT, "bf16_split": _lib.SKH_BF16_SPLIT}
@@ -137,3 +137,28 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     if potentials:
         return S.value, dict(f=f, g=g, p=p, q=q), st.as_dict()
     return S.value
+
+
+def kmeans(x, w=None, k: int = None, iters: int = 10) -> dict:
+    """K-means coarse scale of a cloud (Section 2, coarse-to-fine strategy), on the GPU.
+
+    Returns dict(centres (k, d), masses (k,), labels (n,), perm (n,), offsets (k+1,)).
+    k defaults to ceil(sqrt(n)).
+    """
+    x = _as_points(x, "x")
+    n, d = x.shape
+    if k is None:
+        k = max(1, math.ceil(math.sqrt(n)))
+    wt = _as_vec(w, n, "w", x.device) if w is not None else None
+    dev = x.device
+    out = dict(centres=torch.empty((k, d), dtype=torch.float32, device=dev),
+               masses=torch.empty(k, dtype=torch.float32, device=dev),
+               labels=torch.empty(n, dtype=torch.int32, device=dev),
+               perm=torch.empty(n, dtype=torch.int32, device=dev),
+               offsets=torch.empty(k + 1, dtype=torch.int32, device=dev))
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_kmeans(ctx, _ptr(x), _ptr(wt), n, d, int(k), int(iters),
+                                _ptr(out["centres"]), _ptr(out["masses"]), _ptr(out["labels"]),
+                                _ptr(out["perm"]), _ptr(out["offsets"]))
+    _lib.check(rc, ctx)
+    return out

@@ -20,8 +20,8 @@
 struct skh_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
+    void *ws[2] = {nullptr, nullptr};  // setup buffers, loop buffers
+    size_t ws_bytes[2] = {0, 0};
     void *host = nullptr;  // pinned, kHostBytes
     int num_cus = 256;
     std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches
@@ -71,22 +71,22 @@ struct Carver {
     }
 };
 
-int ensure_ws(skh_ctx *ctx, size_t bytes) {
-    if (bytes <= ctx->ws_bytes) return SKH_OK;
+int ensure_ws(skh_ctx *ctx, int slot, size_t bytes) {
+    if (bytes <= ctx->ws_bytes[slot]) return SKH_OK;
     SKH_HIP(hipStreamSynchronize(ctx->stream));
-    if (ctx->ws) {
-        SKH_HIP(hipFree(ctx->ws));
-        ctx->ws = nullptr;
-        ctx->ws_bytes = 0;
+    if (ctx->ws[slot]) {
+        SKH_HIP(hipFree(ctx->ws[slot]));
+        ctx->ws[slot] = nullptr;
+        ctx->ws_bytes[slot] = 0;
     }
     size_t want = bytes + bytes / 8;
-    if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+    if (hipMalloc(&ctx->ws[slot], want) != hipSuccess) {
         (void)hipGetLastError();
-        ctx->ws = nullptr;
+        ctx->ws[slot] = nullptr;
         return fail(ctx, SKH_ENOMEM,
                     "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
-    ctx->ws_bytes = want;
+    ctx->ws_bytes[slot] = want;
     return SKH_OK;
 }
 
@@ -124,13 +124,71 @@ int ensure_events(skh_ctx *ctx, size_t count) {
     return SKH_OK;
 }
 
-// Bounding box, centre, masses and validation of one or two clouds; results
-// land in ctx->host: floats [lo 64 | hi 64 | centre 64], then masses, then bad counts.
-struct BBoxOut {
-    float lo[64], hi[64];
-    double mass[2];
-    int bad[4];
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int64_t kMaxPoints = 1 << 28;
+constexpr int kKmeansIters = 10;
+
+// Number of K-means clusters for n points: ceil(sqrt(n)), at most 4096.
+int kmeans_k(int64_t n) {
+    int k = (int)std::ceil(std::sqrt((double)n));
+    if (k < 1) k = 1;
+    if (k > 4096) k = 4096;
+    return k;
+}
+
+// Device buffers of one cloud in the cluster-sorted, 32-padded layout.
+struct Clustered {
+    int n = 0, k = 0, n_pad_max = 0, n_pad = 0;
+    float *C = nullptr, *cmass = nullptr, *radius = nullptr;  // k x kp, k, k
+    int *kws = nullptr;                                       // K-means workspace
+    int *psize = nullptr, *poff = nullptr, *ssum = nullptr;   // k + 1, k + 1, scan sums
+    int *perm_pad = nullptr, *blk = nullptr;                  // n_pad_max, n_pad_max / 32
+    float *Xf = nullptr;                                      // n_pad_max x kp
+    __hip_bfloat16 *Yhi = nullptr, *Ylo = nullptr;            // n_pad_max x kp
+    float *hn = nullptr, *lw = nullptr, *wp = nullptr;        // n_pad_max
+    int *perm = nullptr, *off = nullptr;                      // inside kws, set by K-means
+
+    void carve(Carver &c, int n_, int kp) {
+        n = n_;
+        k = kmeans_k(n_);
+        n_pad_max = n_ + 31 * k;
+        C = c.take<float>((size_t)k * kp);
+        cmass = c.take<float>(k);
+        radius = c.take<float>(k);
+        kws = c.take<int>(skh::kmeans_workspace_ints(n_, k));
+        psize = c.take<int>(k + 1);
+        poff = c.take<int>(k + 1);
+        ssum = c.take<int>(skh::scan_sums_len(k + 1));
+        perm_pad = c.take<int>(n_pad_max);
+        blk = c.take<int>(n_pad_max / 32 + 1);
+        Xf = c.take<float>((size_t)n_pad_max * kp);
+        Yhi = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
+        Ylo = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
+        hn = c.take<float>(n_pad_max);
+        lw = c.take<float>(n_pad_max);
+        wp = c.take<float>(n_pad_max);
+    }
 };
+
+// K-means of a packed cloud and the padded cluster sizes (poff[k] = n_pad).
+int cluster_start(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, int kp,
+                  hipStream_t s) {
+    SKH_HIP(skh::run_kmeans(X, w, cl.n, kp, cl.k, kKmeansIters, cl.C, cl.cmass, cl.radius, cl.kws,
+                            &cl.perm, &cl.off, s));
+    SKH_HIP(skh::build_padded_layout(cl.perm, cl.off, cl.k, cl.psize, cl.poff, cl.ssum, s));
+    return SKH_OK;
+}
+
+// Gathers the cloud into the padded order once cl.n_pad is known on the host.
+int cluster_finish(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, int kp,
+                   hipStream_t s) {
+    if (cl.n_pad < cl.n || cl.n_pad > cl.n_pad_max)
+        return fail(ctx, SKH_EHIP, "inconsistent padded cluster layout");
+    SKH_HIP(skh::fill_padded_layout(cl.perm, cl.off, cl.poff, cl.k, cl.perm_pad, cl.blk, s));
+    SKH_HIP(skh::launch_pack_padded(X, w, cl.perm_pad, cl.blk, cl.C, cl.n_pad, kp, cl.Xf, cl.Yhi,
+                                    cl.Ylo, cl.hn, cl.lw, cl.wp, s));
+    return SKH_OK;
+}
 
 }  // namespace
 
@@ -184,7 +242,8 @@ void skh_destroy(skh_ctx *ctx) {
     {
         DeviceGuard guard(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        if (ctx->ws) (void)hipFree(ctx->ws);
+        for (int k = 0; k < 2; ++k)
+            if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
         if (ctx->host) (void)hipHostFree(ctx->host);
         for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     }
@@ -207,59 +266,105 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     if (!ctx) return SKH_EINVAL;
     if (!x || !y || !w || !h || !out) return fail(ctx, SKH_EINVAL, "NULL array argument");
     if (n < 1 || m < 1) return fail(ctx, SKH_EINVAL, "n and m must be >= 1");
-    if (n > INT32_MAX / 2 || m > INT32_MAX / 2) return fail(ctx, SKH_EINVAL, "n or m too large");
+    if (n > kMaxPoints || m > kMaxPoints) return fail(ctx, SKH_EINVAL, "n or m too large");
     if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ctx, SKH_EINVAL, "eps must be > 0");
     if (!(lam > 0.0) || lam > 1.0) return fail(ctx, SKH_EINVAL, "lam must be in (0, 1]");
     if (precision != SKH_FP32 && precision != SKH_BF16_SPLIT)
         return fail(ctx, SKH_EINVAL, "unknown precision");
+    const bool split = precision == SKH_BF16_SPLIT;
+    const int kp = split ? skh::packed_width_bf16(d) : skh::packed_width(d);
+    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 61");
     DeviceGuard guard(ctx->device);
-    const int kp = skh::packed_width(d);
+    hipStream_t s = ctx->stream;
+    const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
+
+    // Phase A: bounding box, packing, and (split path) clustering of the columns.
+    float *Xp, *Yp, *hnx, *hny, *lwy, *plo, *phi, *lohi;
+    double *pmass, *mass;
+    int *pbad, *bad;
+    Clustered cy;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[0] : nullptr);
+        Xp = c.take<float>((size_t)n * kp);
+        Yp = c.take<float>((size_t)m * kp);
+        hnx = c.take<float>(n);
+        hny = c.take<float>(m);
+        lwy = c.take<float>(m);
+        plo = c.take<float>((size_t)(nbx + nby) * 64);
+        phi = c.take<float>((size_t)(nbx + nby) * 64);
+        pmass = c.take<double>(nbx + nby);
+        pbad = c.take<int>(2 * (nbx + nby));
+        lohi = c.take<float>(192);
+        mass = c.take<double>(2);
+        bad = c.take<int>(4);
+        if (split) cy.carve(c, (int)m, kp);
+        if (!pass) {
+            int rc = ensure_ws(ctx, 0, c.off);
+            if (rc) return rc;
+        }
+    }
+    SKH_HIP(skh::launch_bbox_partial(x, nullptr, n, d, plo, phi, pmass, pbad, s));
+    SKH_HIP(skh::launch_bbox_partial(y, w, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
+                                     pmass + nbx, pbad + 2 * nbx, s));
+    SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nbx, nby, d, lohi, mass, bad, s));
+    SKH_HIP(skh::launch_pack(x, nullptr, n, d, kp, lohi + 128, Xp, hnx, nullptr, s));
+    SKH_HIP(skh::launch_pack(y, w, m, d, kp, lohi + 128, Yp, hny, lwy, s));
+    const float *cols_u_lw = lwy, *cols_hn = hny, *h_cols = h;
+    int m_cols = (int)m;
+    if (split) {
+        int rc = cluster_start(ctx, cy, Yp, w, kp, s);
+        if (rc) return rc;
+        SKH_HIP(hipMemcpyAsync(ctx->host, cy.poff + cy.k, sizeof(int), hipMemcpyDeviceToHost, s));
+        SKH_HIP(hipStreamSynchronize(s));
+        cy.n_pad = *static_cast<int *>(ctx->host);
+        rc = cluster_finish(ctx, cy, Yp, w, kp, s);
+        if (rc) return rc;
+        cols_u_lw = cy.lw;
+        cols_hn = cy.hn;
+        m_cols = cy.n_pad;
+    }
+
+    // Phase B: column offsets, the softmin, the merge.
     skh::SoftminBatch batch{};
     batch.n_jobs = 1;
     batch.d = d;
-    batch.kscale = (float)(1.4426950408889634074 / eps);
+    batch.kscale = (float)(kLog2e / eps);
     batch.job[0].n_rows = (int)n;
-    batch.job[0].n_cols = (int)m;
+    batch.job[0].n_cols = m_cols;
     const int wgs = skh::plan_softmin_batch(batch, target_wgs(ctx));
-    const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
-
+    float *u, *hperm;
+    float2 *part;
     for (int pass = 0; pass < 2; ++pass) {
-        Carver c(pass ? ctx->ws : nullptr);
-        float *Xp = c.take<float>((size_t)n * kp);
-        float *Yp = c.take<float>((size_t)m * kp);
-        float *hnx = c.take<float>(n);
-        float *hny = c.take<float>(m);
-        float *lwy = c.take<float>(m);
-        float *u = c.take<float>(m);
-        float2 *part = c.take<float2>((size_t)batch.job[0].n_chunks * n);
-        float *plo = c.take<float>((size_t)(nbx + nby) * 64);
-        float *phi = c.take<float>((size_t)(nbx + nby) * 64);
-        double *pmass = c.take<double>(nbx + nby);
-        int *pbad = c.take<int>(2 * (nbx + nby));
-        float *lohi = c.take<float>(192);
-        double *mass = c.take<double>(2);
-        int *bad = c.take<int>(4);
+        Carver c(pass ? ctx->ws[1] : nullptr);
+        u = c.take<float>(m_cols);
+        hperm = c.take<float>(m_cols);
+        part = c.take<float2>((size_t)batch.job[0].n_chunks * n);
         if (!pass) {
-            int rc = ensure_ws(ctx, c.off);
+            int rc = ensure_ws(ctx, 1, c.off);
             if (rc) return rc;
-            continue;
         }
-        hipStream_t s = ctx->stream;
-        SKH_HIP(skh::launch_bbox_partial(x, nullptr, n, d, plo, phi, pmass, pbad, s));
-        SKH_HIP(skh::launch_bbox_partial(y, w, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
-                                         pmass + nbx, pbad + 2 * nbx, s));
-        SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nbx, nby, d, lohi, mass, bad, s));
-        SKH_HIP(skh::launch_pack(x, nullptr, n, d, kp, lohi + 128, Xp, hnx, nullptr, s));
-        SKH_HIP(skh::launch_pack(y, w, m, d, kp, lohi + 128, Yp, hny, lwy, s));
-        SKH_HIP(skh::launch_col_offsets(lwy, h, hny, m, eps, u, s));
-        batch.job[0].rows = Xp;
-        batch.job[0].cols = Yp;
-        batch.job[0].u = u;
-        batch.job[0].part = part;
-        SKH_HIP(skh::launch_softmin(batch, kp, precision, wgs, s));
-        SKH_HIP(skh::launch_softmin_finish(part, batch.job[0].n_chunks, n, hnx, eps, lam, out, s));
     }
+    if (split) {
+        SKH_HIP(skh::launch_permute(h, cy.perm_pad, cy.n_pad, hperm, s));
+        h_cols = hperm;
+    }
+    SKH_HIP(skh::launch_col_offsets(cols_u_lw, h_cols, cols_hn, m_cols, eps, u, s));
+    skh::SoftminJob &J = batch.job[0];
+    J.rows = Xp;
+    J.u = u;
+    J.part = part;
+    if (split) {
+        J.cols_hi = cy.Yhi;
+        J.cols_lo = cy.Ylo;
+        J.col_blk_cluster = cy.blk;
+        J.col_centroids = cy.C;
+        SKH_HIP(skh::launch_softmin_bf16(batch, kp, wgs, s));
+    } else {
+        J.cols = Yp;
+        SKH_HIP(skh::launch_softmin(batch, kp, precision, wgs, s));
+    }
+    SKH_HIP(skh::launch_softmin_finish(part, J.n_chunks, n, hnx, eps, lam, out, s));
     return SKH_OK;
 }
 
@@ -271,7 +376,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     const auto t_start = std::chrono::steady_clock::now();
     if (!x || !a || !y || !b || !params) return fail(ctx, SKH_EINVAL, "NULL argument");
     if (n < 1 || m < 1) return fail(ctx, SKH_EINVAL, "n and m must be >= 1");
-    if (n > INT32_MAX / 2 || m > INT32_MAX / 2) return fail(ctx, SKH_EINVAL, "n or m too large");
+    if (n > kMaxPoints || m > kMaxPoints) return fail(ctx, SKH_EINVAL, "n or m too large");
     if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
     const skh_params P = *params;
     if (!(P.blur > 0.0) || !std::isfinite(P.blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
@@ -286,44 +391,30 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         if (P.reserved[k]) return fail(ctx, SKH_EINVAL, "reserved params must be zero");
     if (P.init && (!f || !g || !p || !q))
         return fail(ctx, SKH_EINVAL, "init requires f, g, p and q");
+    const bool split = P.precision == SKH_BF16_SPLIT;
+    const int kp = split ? skh::packed_width_bf16(d) : skh::packed_width(d);
+    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 61");
     const int check_every = P.check_every < 1 ? 1 : P.check_every;
     const bool balanced = is_balanced(P.reach);
     const double rho = balanced ? 0.0 : P.reach * P.reach;
 
     DeviceGuard guard(ctx->device);
     hipStream_t s = ctx->stream;
-    const int kp = skh::packed_width(d);
-    skh::SoftminBatch batch{};
-    batch.n_jobs = 4;
-    batch.d = d;
-    // job 0: a~^{aa} (rows x, cols x); job 1: b~^{bb} (rows y, cols y);
-    // job 2: a~^{a->b} (rows y, cols x); job 3: b~^{b->a} (rows x, cols y).
-    const int64_t nr[4] = {n, m, m, n}, nc[4] = {n, m, n, m};
-    for (int k = 0; k < 4; ++k) {
-        batch.job[k].n_rows = (int)nr[k];
-        batch.job[k].n_cols = (int)nc[k];
-    }
-    const int wgs = skh::plan_softmin_batch(batch, target_wgs(ctx));
     const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
-    const int fbx = skh::finish_blocks(n), fby = skh::finish_blocks(m);
 
-    float *Xp = nullptr, *Yp = nullptr, *hnx = nullptr, *hny = nullptr, *lwx = nullptr,
-          *lwy = nullptr, *u[4] = {nullptr, nullptr, nullptr, nullptr};
-    float2 *part[4] = {nullptr, nullptr, nullptr, nullptr};
-    float *plo = nullptr, *phi = nullptr, *lohi = nullptr;
-    double *pmass = nullptr, *mass = nullptr, *acc = nullptr, *sums = nullptr;
-    int *pbad = nullptr, *bad = nullptr;
-    float *pot[4] = {f, g, p, q};
+    // ---- Phase A: bounding box, validation, packing, clustering (split path) ----
+    float *Xp, *Yp, *hnx, *hny, *lwx, *lwy, *plo, *phi, *lohi;
+    double *pmass, *mass;
+    int *pbad, *bad;
+    Clustered cx, cy;
     for (int pass = 0; pass < 2; ++pass) {
-        Carver c(pass ? ctx->ws : nullptr);
+        Carver c(pass ? ctx->ws[0] : nullptr);
         Xp = c.take<float>((size_t)n * kp);
         Yp = c.take<float>((size_t)m * kp);
         hnx = c.take<float>(n);
         hny = c.take<float>(m);
         lwx = c.take<float>(n);
         lwy = c.take<float>(m);
-        for (int k = 0; k < 4; ++k) u[k] = c.take<float>(nc[k]);
-        for (int k = 0; k < 4; ++k) part[k] = c.take<float2>((size_t)batch.job[k].n_chunks * nr[k]);
         plo = c.take<float>((size_t)(nbx + nby) * 64);
         phi = c.take<float>((size_t)(nbx + nby) * 64);
         pmass = c.take<double>(nbx + nby);
@@ -331,22 +422,15 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         lohi = c.take<float>(192);
         mass = c.take<double>(2);
         bad = c.take<int>(4);
-        acc = c.take<double>((size_t)(fbx + fby) * 4);
-        sums = c.take<double>(8);
-        // potentials the caller did not ask for live in the workspace
-        const int64_t plen[4] = {n, m, n, m};
-        for (int k = 0; k < 4; ++k) {
-            float *t = c.take<float>(plen[k]);
-            if (pass && !pot[k]) pot[k] = t;
+        if (split) {
+            cx.carve(c, (int)n, kp);
+            cy.carve(c, (int)m, kp);
         }
         if (!pass) {
-            int rc = ensure_ws(ctx, c.off);
+            int rc = ensure_ws(ctx, 0, c.off);
             if (rc) return rc;
         }
     }
-    float *F = pot[0], *G = pot[1], *Pp = pot[2], *Q = pot[3];
-
-    // Bounding box, centre, masses, validation (one sync).
     SKH_HIP(skh::launch_bbox_partial(x, a, n, d, plo, phi, pmass, pbad, s));
     SKH_HIP(skh::launch_bbox_partial(y, b, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
                                      pmass + nbx, pbad + 2 * nbx, s));
@@ -382,35 +466,117 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     SKH_HIP(skh::launch_pack(x, a, n, d, kp, lohi + 128, Xp, hnx, lwx, s));
     SKH_HIP(skh::launch_pack(y, b, m, d, kp, lohi + 128, Yp, hny, lwy, s));
-    if (!P.init) {
-        SKH_HIP(hipMemsetAsync(F, 0, n * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(Pp, 0, n * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(G, 0, m * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(Q, 0, m * sizeof(float), s));
+    // point sets the loop runs on: the caller's order (FP32 path) or the
+    // cluster-sorted padded order (split path)
+    int64_t nn = n, mm = m;
+    const float *rowx = Xp, *rowy = Yp, *hnX = hnx, *hnY = hny, *lwX = lwx, *lwY = lwy, *wX = a,
+                *wY = b;
+    if (split) {
+        int rc = cluster_start(ctx, cx, Xp, a, kp, s);
+        if (rc) return rc;
+        rc = cluster_start(ctx, cy, Yp, b, kp, s);
+        if (rc) return rc;
+        SKH_HIP(hipMemcpyAsync(hb + 1024, cx.poff + cx.k, sizeof(int), hipMemcpyDeviceToHost, s));
+        SKH_HIP(hipMemcpyAsync(hb + 1028, cy.poff + cy.k, sizeof(int), hipMemcpyDeviceToHost, s));
+        SKH_HIP(hipStreamSynchronize(s));
+        cx.n_pad = *reinterpret_cast<int *>(hb + 1024);
+        cy.n_pad = *reinterpret_cast<int *>(hb + 1028);
+        rc = cluster_finish(ctx, cx, Xp, a, kp, s);
+        if (rc) return rc;
+        rc = cluster_finish(ctx, cy, Yp, b, kp, s);
+        if (rc) return rc;
+        nn = cx.n_pad;
+        mm = cy.n_pad;
+        rowx = cx.Xf;
+        rowy = cy.Xf;
+        hnX = cx.hn;
+        hnY = cy.hn;
+        lwX = cx.lw;
+        lwY = cy.lw;
+        wX = cx.wp;
+        wY = cy.wp;
+    }
+
+    // ---- Phase B: loop buffers ----
+    skh::SoftminBatch batch{};
+    batch.n_jobs = 4;
+    batch.d = d;
+    // job 0: a~^{aa} (rows x, cols x); job 1: b~^{bb} (rows y, cols y);
+    // job 2: a~^{a->b} (rows y, cols x); job 3: b~^{b->a} (rows x, cols y).
+    const int64_t nr[4] = {nn, mm, mm, nn}, nc[4] = {nn, mm, nn, mm};
+    for (int k = 0; k < 4; ++k) {
+        batch.job[k].n_rows = (int)nr[k];
+        batch.job[k].n_cols = (int)nc[k];
+    }
+    const int wgs = skh::plan_softmin_batch(batch, target_wgs(ctx));
+    const int fbx = skh::finish_blocks(nn), fby = skh::finish_blocks(mm);
+    float *u[4];
+    float2 *part[4];
+    double *acc, *sums;
+    float *pot[4] = {f, g, p, q};
+    const int64_t plen[4] = {nn, mm, nn, mm};
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[1] : nullptr);
+        for (int k = 0; k < 4; ++k) u[k] = c.take<float>(nc[k]);
+        for (int k = 0; k < 4; ++k) part[k] = c.take<float2>((size_t)batch.job[k].n_chunks * nr[k]);
+        acc = c.take<double>((size_t)(fbx + fby) * 4);
+        sums = c.take<double>(8);
+        // potentials live in the workspace unless the caller's buffers can be used in place
+        for (int k = 0; k < 4; ++k) {
+            float *t = c.take<float>(plen[k]);
+            if (pass && (split || !pot[k])) pot[k] = t;
+        }
+        if (!pass) {
+            int rc = ensure_ws(ctx, 1, c.off);
+            if (rc) return rc;
+        }
+    }
+    float *F = pot[0], *G = pot[1], *Pp = pot[2], *Q = pot[3];
+    if (P.init) {
+        if (split) {
+            SKH_HIP(skh::launch_permute(f, cx.perm_pad, cx.n_pad, F, s));
+            SKH_HIP(skh::launch_permute(p, cx.perm_pad, cx.n_pad, Pp, s));
+            SKH_HIP(skh::launch_permute(g, cy.perm_pad, cy.n_pad, G, s));
+            SKH_HIP(skh::launch_permute(q, cy.perm_pad, cy.n_pad, Q, s));
+        }
+    } else {
+        SKH_HIP(hipMemsetAsync(F, 0, nn * sizeof(float), s));
+        SKH_HIP(hipMemsetAsync(Pp, 0, nn * sizeof(float), s));
+        SKH_HIP(hipMemsetAsync(G, 0, mm * sizeof(float), s));
+        SKH_HIP(hipMemsetAsync(Q, 0, mm * sizeof(float), s));
     }
     {
         const double e0 = sigma_at(0) * sigma_at(0);
-        SKH_HIP(skh::launch_col_offsets(lwx, Pp, hnx, n, e0, u[0], s));
-        SKH_HIP(skh::launch_col_offsets(lwy, Q, hny, m, e0, u[1], s));
-        SKH_HIP(skh::launch_col_offsets(lwx, F, hnx, n, e0, u[2], s));
-        SKH_HIP(skh::launch_col_offsets(lwy, G, hny, m, e0, u[3], s));
+        SKH_HIP(skh::launch_col_offsets(lwX, Pp, hnX, nn, e0, u[0], s));
+        SKH_HIP(skh::launch_col_offsets(lwY, Q, hnY, mm, e0, u[1], s));
+        SKH_HIP(skh::launch_col_offsets(lwX, F, hnX, nn, e0, u[2], s));
+        SKH_HIP(skh::launch_col_offsets(lwY, G, hnY, mm, e0, u[3], s));
     }
-    const float *rowp[4] = {Xp, Yp, Yp, Xp}, *colp[4] = {Xp, Yp, Xp, Yp};
+    const float *rowp[4] = {rowx, rowy, rowy, rowx}, *colp[4] = {Xp, Yp, Xp, Yp};
+    const Clustered *colc[4] = {&cx, &cy, &cx, &cy};
     for (int k = 0; k < 4; ++k) {
-        batch.job[k].rows = rowp[k];
-        batch.job[k].cols = colp[k];
-        batch.job[k].u = u[k];
-        batch.job[k].part = part[k];
+        skh::SoftminJob &J = batch.job[k];
+        J.rows = rowp[k];
+        J.u = u[k];
+        J.part = part[k];
+        if (split) {
+            J.cols_hi = colc[k]->Yhi;
+            J.cols_lo = colc[k]->Ylo;
+            J.col_blk_cluster = colc[k]->blk;
+            J.col_centroids = colc[k]->C;
+        } else {
+            J.cols = colp[k];
+        }
     }
     skh::FinishSide sx{}, sy{};
     sx.part_self = part[0];
     sx.part_cross = part[3];
     sx.chunks_self = batch.job[0].n_chunks;
     sx.chunks_cross = batch.job[3].n_chunks;
-    sx.n = n;
-    sx.hn = hnx;
-    sx.lw = lwx;
-    sx.w = a;
+    sx.n = nn;
+    sx.hn = hnX;
+    sx.lw = lwX;
+    sx.w = wX;
     sx.pot_self = Pp;
     sx.pot_cross = F;
     sx.u_self = u[0];
@@ -419,10 +585,10 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     sy.part_cross = part[2];
     sy.chunks_self = batch.job[1].n_chunks;
     sy.chunks_cross = batch.job[2].n_chunks;
-    sy.n = m;
-    sy.hn = hny;
-    sy.lw = lwy;
-    sy.w = b;
+    sy.n = mm;
+    sy.hn = hnY;
+    sy.lw = lwY;
+    sy.w = wY;
     sy.pot_self = Q;
     sy.pot_cross = G;
     sy.u_self = u[1];
@@ -435,15 +601,19 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     double err = -1.0, eps = P.blur * P.blur, pairs = 0.0;
     int it = 0, checks = 0;
     bool converged = false;
+    // pairs of real points (padding excluded)
     const double pairs_per_iter = (double)n * n + (double)m * m + 2.0 * (double)n * m;
     for (; it < cap; ++it) {
         const double sigma = sigma_at(it);
         eps = sigma * sigma;
         const double lam = damping(sigma, P.reach);
         const double sn = sigma_at(it + 1);
-        batch.kscale = (float)(1.4426950408889634074 / eps);
+        batch.kscale = (float)(kLog2e / eps);
         if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * it], s));
-        SKH_HIP(skh::launch_softmin(batch, kp, P.precision, wgs, s));
+        if (split)
+            SKH_HIP(skh::launch_softmin_bf16(batch, kp, wgs, s));
+        else
+            SKH_HIP(skh::launch_softmin(batch, kp, P.precision, wgs, s));
         if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * it + 1], s));
         pairs += pairs_per_iter;
         bool check = (it == cap - 1);
@@ -475,10 +645,16 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     // eq. (6) at eps = blur^2, FP64 on the device.
     int nbd = 0;
-    SKH_HIP(skh::launch_divergence_terms(a, F, Pp, n, b, G, Q, m, rho, balanced ? 1 : 0, acc, &nbd,
-                                         s));
+    SKH_HIP(skh::launch_divergence_terms(wX, F, Pp, nn, wY, G, Q, mm, rho, balanced ? 1 : 0, acc,
+                                         &nbd, s));
     SKH_HIP(skh::launch_sum_partials(acc, nbd, 4, sums, s));
     SKH_HIP(hipMemcpyAsync(hb + 1024, sums, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (split) {
+        float *outs[4] = {f, g, p, q};
+        const Clustered *cl[4] = {&cx, &cy, &cx, &cy};
+        for (int k = 0; k < 4; ++k)
+            if (outs[k]) SKH_HIP(skh::launch_unpermute(pot[k], cl[k]->perm_pad, cl[k]->n_pad, outs[k], s));
+    }
     SKH_HIP(hipStreamSynchronize(s));
     double S = *reinterpret_cast<const double *>(hb + 1024);
     const double eps_blur = P.blur * P.blur;
@@ -510,6 +686,55 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     }
     if (!std::isfinite(S)) return fail(ctx, SKH_ENONFINITE, "non-finite divergence");
     if (P.tol > 0.0 && !converged) return SKH_NOT_CONVERGED;
+    return SKH_OK;
+}
+
+int skh_kmeans(skh_ctx *ctx, const float *x, const float *w, int64_t n, int32_t d, int32_t k,
+               int32_t iters, float *centres, float *masses, int32_t *labels, int32_t *perm,
+               int32_t *offsets) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x) return fail(ctx, SKH_EINVAL, "NULL x");
+    if (n < 1 || n > kMaxPoints) return fail(ctx, SKH_EINVAL, "n out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    if (k < 1 || k > 4096 || k > n) return fail(ctx, SKH_EINVAL, "k must be in [1, min(n, 4096)]");
+    if (iters < 0) return fail(ctx, SKH_EINVAL, "iters must be >= 0");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int kp = skh::packed_width(d);
+    const int nb = skh::bbox_blocks(n);
+    float *Xp, *hn, *plo, *phi, *lohi, *C, *cm;
+    double *pmass, *mass;
+    int *pbad, *bad, *kws;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[0] : nullptr);
+        Xp = c.take<float>((size_t)n * kp);
+        hn = c.take<float>(n);
+        plo = c.take<float>((size_t)nb * 64);
+        phi = c.take<float>((size_t)nb * 64);
+        pmass = c.take<double>(nb);
+        pbad = c.take<int>(2 * nb);
+        lohi = c.take<float>(192);
+        mass = c.take<double>(2);
+        bad = c.take<int>(4);
+        C = c.take<float>((size_t)k * kp);
+        cm = c.take<float>(k);
+        kws = c.take<int>(skh::kmeans_workspace_ints((int)n, k));
+        if (!pass) {
+            int rc = ensure_ws(ctx, 0, c.off);
+            if (rc) return rc;
+        }
+    }
+    SKH_HIP(skh::launch_bbox_partial(x, w, n, d, plo, phi, pmass, pbad, s));
+    SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nb, 0, d, lohi, mass, bad, s));
+    SKH_HIP(skh::launch_pack(x, w, n, d, kp, lohi + 128, Xp, hn, nullptr, s));
+    int *dperm = nullptr, *doff = nullptr;
+    SKH_HIP(skh::run_kmeans(Xp, w, (int)n, kp, k, iters, C, cm, nullptr, kws, &dperm, &doff, s));
+    if (centres) SKH_HIP(skh::launch_unpack_centres(C, k, d, kp, lohi + 128, centres, s));
+    if (masses) SKH_HIP(hipMemcpyAsync(masses, cm, k * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (labels) SKH_HIP(hipMemcpyAsync(labels, kws, n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    if (perm) SKH_HIP(hipMemcpyAsync(perm, dperm, n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    if (offsets)
+        SKH_HIP(hipMemcpyAsync(offsets, doff, (k + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
     return SKH_OK;
 }
 

@@ -1,0 +1,435 @@
+// K-means coarse scale and the cluster-sorted layout (coarse-to-fine strategy,
+// Section 2: "a simple K-means algorithm" for the coarse subsampling).
+//
+// Lloyd iterations on the device:
+//   assign   label_i = argmin_c |c|^2/2 - <x_i, c>     (ties -> lowest c)
+//   sort     stable counting sort by label (per-block counts, one exclusive
+//            scan over label-major counts, in-block ranks) -> permutation
+//   update   c = alpha-weighted mean of its members, summed in FP64 in a fixed
+//            order over the sorted members; an empty cluster keeps its centre
+// Every step is deterministic (integer LDS atomics only count).
+//
+// The padded layout places every cluster at a multiple of 32 points so that a
+// 32-column MFMA block never spans two clusters; padding points carry zero
+// weight (log-weight -inf).
+#include "skh_internal.h"
+
+namespace skh {
+
+constexpr int kT = 256;
+
+template <int KP>
+__global__ __launch_bounds__(kT) void k_kmeans_assign(const float *__restrict__ X, int n,
+                                                      const float *__restrict__ C, int k,
+                                                      int *__restrict__ label) {
+    constexpr int CB = 32;  // centroids per LDS chunk
+    __shared__ float sc[CB][KP];
+    __shared__ float scn[CB];
+    const int i = blockIdx.x * kT + threadIdx.x;
+    float xr[KP];
+#pragma unroll
+    for (int d = 0; d < KP; ++d) xr[d] = i < n ? X[(size_t)i * KP + d] : 0.0f;
+    float best = __builtin_huge_valf();
+    int bl = 0;
+    for (int c0 = 0; c0 < k; c0 += CB) {
+        __syncthreads();
+        const int cnt = min(CB, k - c0);
+        for (int e = threadIdx.x; e < cnt * KP; e += kT) sc[e / KP][e % KP] = C[(size_t)c0 * KP + e];
+        __syncthreads();
+        if (threadIdx.x < cnt) {
+            float s = 0.0f;
+#pragma unroll
+            for (int d = 0; d < KP; ++d) s = fmaf(sc[threadIdx.x][d], sc[threadIdx.x][d], s);
+            scn[threadIdx.x] = 0.5f * s;
+        }
+        __syncthreads();
+        for (int c = 0; c < cnt; ++c) {
+            float v = scn[c];
+#pragma unroll
+            for (int d = 0; d < KP; ++d) v = fmaf(-xr[d], sc[c][d], v);
+            if (v < best) {
+                best = v;
+                bl = c0 + c;
+            }
+        }
+    }
+    if (i < n) label[i] = bl;
+}
+
+// counts[c * nb + b] = number of points of block b (kT points) with label c.
+__global__ __launch_bounds__(kT) void k_label_count(const int *__restrict__ label, int n, int k,
+                                                    int nb, int *__restrict__ counts) {
+    extern __shared__ int hist[];
+    for (int c = threadIdx.x; c < k; c += kT) hist[c] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * kT + threadIdx.x;
+    if (i < n) atomicAdd(&hist[label[i]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += kT) counts[(size_t)c * nb + blockIdx.x] = hist[c];
+}
+
+// Stable scatter: position = offs[label * nb + block] + rank among earlier
+// points of the block with the same label.
+__global__ __launch_bounds__(kT) void k_label_scatter(const int *__restrict__ label, int n, int nb,
+                                                      const int *__restrict__ offs,
+                                                      int *__restrict__ perm,
+                                                      int *__restrict__ sorted_label) {
+    __shared__ int sl[kT];
+    const int i = blockIdx.x * kT + threadIdx.x;
+    const int lab = i < n ? label[i] : -1;
+    sl[threadIdx.x] = lab;
+    __syncthreads();
+    if (i < n) {
+        int r = 0;
+        for (int t = 0; t < (int)threadIdx.x; ++t) r += (sl[t] == lab);
+        const int pos = offs[(size_t)lab * nb + blockIdx.x] + r;
+        perm[pos] = i;
+        sorted_label[pos] = lab;
+    }
+}
+
+// Exclusive scan of int arrays: three phases over blocks of 1024 elements.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kT) void k_scan_block_sums(const int *__restrict__ in, int64_t len,
+                                                        int *__restrict__ sums) {
+    __shared__ int sh[kT];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    int s = 0;
+    for (int e = threadIdx.x; e < kScanBlock; e += kT)
+        if (base + e < len) s += in[base + e];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kT / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = sh[0];
+}
+
+// One block: exclusive scan of nsum block sums in place; total in sums[nsum].
+__global__ __launch_bounds__(kT) void k_scan_sums(int *sums, int nsum) {
+    __shared__ int sh[kT];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nsum; b0 += kT) {
+        const int idx = b0 + threadIdx.x;
+        const int v = idx < nsum ? sums[idx] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kT; o <<= 1) {  // inclusive Hillis-Steele
+            const int t = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (idx < nsum) sums[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kT - 1) carry += sh[kT - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nsum] = carry;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_apply(const int *__restrict__ in, int64_t len,
+                                                   const int *__restrict__ sums,
+                                                   int *__restrict__ out) {
+    __shared__ int sh[kT];
+    __shared__ int carry;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    if (threadIdx.x == 0) carry = sums[blockIdx.x];
+    __syncthreads();
+    for (int e0 = 0; e0 < kScanBlock; e0 += kT) {
+        const int64_t idx = base + e0 + threadIdx.x;
+        const int v = idx < len ? in[idx] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kT; o <<= 1) {
+            const int t = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (idx < len) out[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kT - 1) carry += sh[kT - 1];
+        __syncthreads();
+    }
+}
+
+int scan_sums_len(int64_t len) { return (int)((len + kScanBlock - 1) / kScanBlock) + 1; }
+
+hipError_t launch_exclusive_scan(const int *in, int64_t len, int *sums, int *out, hipStream_t s) {
+    const int nblk = (int)((len + kScanBlock - 1) / kScanBlock);
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(nblk), dim3(kT), 0, s, in, len, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kT), 0, s, sums, nblk);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kT), 0, s, in, len, sums, out);
+    return hipGetLastError();
+}
+
+// One block per cluster: alpha-weighted mean of the members (sorted range
+// [off[c], off[c+1]) of perm), FP64 accumulation in a fixed order.  Members with
+// zero weight do not move the centre; a cluster with no mass keeps its centre.
+// Also writes the cluster mass (FP32 of the FP64 sum).
+template <int KP>
+__global__ __launch_bounds__(kT) void k_centroid_update(const float *__restrict__ X,
+                                                        const float *__restrict__ w,
+                                                        const int *__restrict__ perm,
+                                                        const int *__restrict__ off,
+                                                        float *__restrict__ C,
+                                                        float *__restrict__ cmass) {
+    __shared__ double sh[4][KP];
+    __shared__ double shm[4];
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int beg = off[c], end = off[c + 1];
+    double acc = 0.0, m = 0.0;
+    for (int p = beg + wave; p < end; p += 4) {
+        const int i = perm[p];
+        const double wi = w ? (double)w[i] : 1.0;
+        if (lane < KP) acc += wi * (double)X[(size_t)i * KP + lane];
+        m += wi;
+    }
+    if (lane < KP) sh[wave][lane] = acc;
+    if (lane == 0) shm[wave] = m;
+    __syncthreads();
+    if (threadIdx.x < KP) {
+        const int d = threadIdx.x;
+        const double mass = ((shm[0] + shm[1]) + shm[2]) + shm[3];
+        const double sum = ((sh[0][d] + sh[1][d]) + sh[2][d]) + sh[3][d];
+        if (mass > 0.0) C[(size_t)c * KP + d] = (float)(sum / mass);
+        if (d == 0 && cmass) cmass[c] = (float)mass;
+    }
+}
+
+// Radius of each cluster: max distance of a member to its centre.
+template <int KP>
+__global__ __launch_bounds__(kT) void k_cluster_radius(const float *__restrict__ X,
+                                                       const int *__restrict__ perm,
+                                                       const int *__restrict__ off,
+                                                       const float *__restrict__ C,
+                                                       float *__restrict__ radius) {
+    __shared__ float sh[kT];
+    const int c = blockIdx.x;
+    float r2 = 0.0f;
+    for (int p = off[c] + threadIdx.x; p < off[c + 1]; p += kT) {
+        const int i = perm[p];
+        float s = 0.0f;
+#pragma unroll
+        for (int d = 0; d < KP; ++d) {
+            const float t = X[(size_t)i * KP + d] - C[(size_t)c * KP + d];
+            s = fmaf(t, t, s);
+        }
+        r2 = fmaxf(r2, s);
+    }
+    sh[threadIdx.x] = r2;
+    __syncthreads();
+    for (int o = kT / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) radius[c] = sqrtf(sh[0]);
+}
+
+__global__ __launch_bounds__(kT) void k_init_centroids(const float *__restrict__ X, int n, int k,
+                                                       int kp, float *__restrict__ C) {
+    const int e = blockIdx.x * kT + threadIdx.x;
+    if (e >= k * kp) return;
+    const int c = e / kp, d = e % kp;
+    const int64_t src = (int64_t)c * n / k;  // evenly strided distinct points
+    C[e] = X[src * kp + d];
+}
+
+// Cluster offsets from the scanned label-major counts: off[c] = offs[c * nb].
+__global__ __launch_bounds__(kT) void k_cluster_offsets(const int *__restrict__ offs, int k, int nb,
+                                                        int n, int *__restrict__ off) {
+    const int c = blockIdx.x * kT + threadIdx.x;
+    if (c < k) off[c] = offs[(size_t)c * nb];
+    if (c == k) off[k] = n;
+}
+
+// Padded sizes (multiple of 32) of each cluster.
+__global__ __launch_bounds__(kT) void k_padded_sizes(const int *__restrict__ off, int k,
+                                                     int *__restrict__ psize) {
+    const int c = blockIdx.x * kT + threadIdx.x;
+    if (c == k) psize[k] = 0;  // the scan below runs over k + 1 entries
+    if (c >= k) return;
+    const int s = off[c + 1] - off[c];
+    psize[c] = (s + 31) & ~31;
+}
+
+// perm_pad[poff[c] + r] = perm[off[c] + r] for r < size, -1 on the padding;
+// blk_cluster[(poff[c] + 32 t) / 32] = c.
+__global__ __launch_bounds__(kT) void k_padded_layout(const int *__restrict__ perm,
+                                                      const int *__restrict__ off,
+                                                      const int *__restrict__ poff, int k,
+                                                      int *__restrict__ perm_pad,
+                                                      int *__restrict__ blk_cluster) {
+    const int c = blockIdx.x;
+    if (c >= k) return;
+    const int beg = off[c], size = off[c + 1] - beg;
+    const int pbeg = poff[c], psize = poff[c + 1] - pbeg;
+    for (int r = threadIdx.x; r < psize; r += kT) perm_pad[pbeg + r] = r < size ? perm[beg + r] : -1;
+    for (int t = threadIdx.x; t < psize / 32; t += kT) blk_cluster[pbeg / 32 + t] = c;
+}
+
+// Gathers one cloud into the padded cluster order.
+//   Xf  : n_pad x KP FP32, centred coordinates (row operand and norms)
+//   Yhi/Ylo : n_pad x KP bf16, hi/lo split of x - c_{cluster} (column operand)
+//   hn, lw, wp : half squared norms, log weights (-inf on padding), weights (0 on padding)
+template <int KP>
+__global__ __launch_bounds__(kT) void k_pack_padded(
+    const float *__restrict__ X, const float *__restrict__ w, const int *__restrict__ perm_pad,
+    const int *__restrict__ blk_cluster, const float *__restrict__ C, int n_pad,
+    float *__restrict__ Xf, __hip_bfloat16 *__restrict__ Yhi, __hip_bfloat16 *__restrict__ Ylo,
+    float *__restrict__ hn, float *__restrict__ lw, float *__restrict__ wp) {
+    const int p = blockIdx.x * kT + threadIdx.x;
+    if (p >= n_pad) return;
+    const int i = perm_pad[p];
+    const int c = blk_cluster[p >> 5];
+    double s = 0.0;
+    for (int d = 0; d < KP; ++d) {
+        const float v = i >= 0 ? X[(size_t)i * KP + d] : 0.0f;
+        Xf[(size_t)p * KP + d] = v;
+        s += (double)v * (double)v;
+        const float dv = i >= 0 ? v - C[(size_t)c * KP + d] : 0.0f;
+        const __hip_bfloat16 hi = __float2bfloat16(dv);
+        const __hip_bfloat16 lo = __float2bfloat16(dv - __bfloat162float(hi));
+        Yhi[(size_t)p * KP + d] = hi;
+        Ylo[(size_t)p * KP + d] = lo;
+    }
+    hn[p] = (float)(0.5 * s);
+    const float wi = i >= 0 ? (w ? w[i] : 1.0f) : 0.0f;
+    wp[p] = wi;
+    lw[p] = wi > 0.0f ? (float)log((double)wi) : -__builtin_huge_valf();
+}
+
+// out[perm_pad[p]] = in[p] for real points; in[p] = src[perm_pad[p]] (0 on padding).
+__global__ __launch_bounds__(kT) void k_unpermute(const float *__restrict__ in,
+                                                  const int *__restrict__ perm_pad, int n_pad,
+                                                  float *__restrict__ out) {
+    const int p = blockIdx.x * kT + threadIdx.x;
+    if (p >= n_pad) return;
+    const int i = perm_pad[p];
+    if (i >= 0) out[i] = in[p];
+}
+__global__ __launch_bounds__(kT) void k_permute(const float *__restrict__ src,
+                                                const int *__restrict__ perm_pad, int n_pad,
+                                                float *__restrict__ out) {
+    const int p = blockIdx.x * kT + threadIdx.x;
+    if (p >= n_pad) return;
+    const int i = perm_pad[p];
+    out[p] = i >= 0 ? src[i] : 0.0f;
+}
+
+// Centres back in the caller's coordinates: out[c*d + t] = C[c*kp + t] + centre[t].
+__global__ __launch_bounds__(kT) void k_unpack_centres(const float *__restrict__ C, int k, int d,
+                                                       int kp, const float *__restrict__ centre,
+                                                       float *__restrict__ out) {
+    const int e = blockIdx.x * kT + threadIdx.x;
+    if (e >= k * d) return;
+    const int c = e / d, t = e % d;
+    out[e] = (float)((double)C[(size_t)c * kp + t] + (double)centre[t]);
+}
+
+static inline unsigned blocks(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+hipError_t launch_unpack_centres(const float *C, int k, int d, int kp, const float *centre,
+                                 float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack_centres, dim3(blocks((int64_t)k * d)), dim3(kT), 0, s, C, k, d, kp,
+                       centre, out);
+    return hipGetLastError();
+}
+
+#define SKH_KP_DISPATCH(kp, KERNEL, ...)                                         \
+    switch (kp) {                                                                \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                   \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                   \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                 \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                 \
+    case 64: hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__); break;                 \
+    default: return hipErrorInvalidValue;                                        \
+    }
+
+size_t kmeans_workspace_ints(int n, int k) {
+    const int nb = (n + kT - 1) / kT;
+    const int64_t len = (int64_t)k * nb;
+    // label, sorted_label, perm, counts, offs, scan sums, off (k+1)
+    return (size_t)n * 3 + (size_t)len * 2 + (size_t)scan_sums_len(len) + (size_t)(k + 1) + 64;
+}
+
+hipError_t run_kmeans(const float *X, const float *w, int n, int kp, int k, int iters, float *C,
+                      float *cmass, float *radius, int *ws, int **perm_out, int **off_out,
+                      hipStream_t s) {
+    const int nb = (n + kT - 1) / kT;
+    const int64_t len = (int64_t)k * nb;
+    int *label = ws;
+    int *slabel = label + n;
+    int *perm = slabel + n;
+    int *counts = perm + n;
+    int *offs = counts + len;
+    int *sums = offs + len;
+    int *off = sums + scan_sums_len(len);
+    hipLaunchKernelGGL(k_init_centroids, dim3(blocks((int64_t)k * kp)), dim3(kT), 0, s, X, n, k, kp,
+                       C);
+    for (int it = 0; it <= iters; ++it) {
+        SKH_KP_DISPATCH(kp, k_kmeans_assign, dim3(blocks(n)), dim3(kT), 0, s, X, n, C, k, label);
+        hipLaunchKernelGGL(k_label_count, dim3(nb), dim3(kT), k * sizeof(int), s, label, n, k, nb,
+                           counts);
+        hipError_t e = launch_exclusive_scan(counts, len, sums, offs, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_label_scatter, dim3(nb), dim3(kT), 0, s, label, n, nb, offs, perm,
+                           slabel);
+        hipLaunchKernelGGL(k_cluster_offsets, dim3(blocks(k + 1)), dim3(kT), 0, s, offs, k, nb, n,
+                           off);
+        // the last pass only sorts by the final centres (labels consistent with C)
+        if (it < iters) {
+            SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C,
+                            cmass);
+        }
+    }
+    // the coarse points are the weighted means of the final clusters, with their masses
+    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C, cmass);
+    if (radius) SKH_KP_DISPATCH(kp, k_cluster_radius, dim3(k), dim3(kT), 0, s, X, perm, off, C, radius);
+    *perm_out = perm;
+    *off_out = off;
+    return hipGetLastError();
+}
+
+hipError_t build_padded_layout(const int *perm, const int *off, int k, int *psize, int *poff,
+                               int *scan_sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_padded_sizes, dim3(blocks(k + 1)), dim3(kT), 0, s, off, k, psize);
+    return launch_exclusive_scan(psize, k + 1, scan_sums, poff, s);
+}
+
+hipError_t fill_padded_layout(const int *perm, const int *off, const int *poff, int k,
+                              int *perm_pad, int *blk_cluster, hipStream_t s) {
+    hipLaunchKernelGGL(k_padded_layout, dim3(k), dim3(kT), 0, s, perm, off, poff, k, perm_pad,
+                       blk_cluster);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pad,
+                              const int *blk_cluster, const float *C, int n_pad, int kp, float *Xf,
+                              __hip_bfloat16 *Yhi, __hip_bfloat16 *Ylo, float *hn, float *lw,
+                              float *wp, hipStream_t s) {
+    SKH_KP_DISPATCH(kp, k_pack_padded, dim3(blocks(n_pad)), dim3(kT), 0, s, X, w, perm_pad,
+                    blk_cluster, C, n_pad, Xf, Yhi, Ylo, hn, lw, wp);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, float *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_unpermute, dim3(blocks(n_pad)), dim3(kT), 0, s, in, perm_pad, n_pad, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(const float *src, const int *perm_pad, int n_pad, float *out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_permute, dim3(blocks(n_pad)), dim3(kT), 0, s, src, perm_pad, n_pad, out);
+    return hipGetLastError();
+}
+
+}  // namespace skh

@@ -2,6 +2,7 @@
 // Not part of the public C ABI (include/skh.h).
 #pragma once
 
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,6 +13,9 @@ namespace skh {
 // minus a common centre (the cost is translation invariant), slot d is
 // reserved for the augmented term of the softmin contraction, the rest is 0.
 int packed_width(int d);
+// Width of the packed rows for the BF16 split path: slots d, d+1, d+2 carry the
+// three bf16 terms of the column offset, and KP is 16, 32 or 64 (0: d too large).
+int packed_width_bf16(int d);
 
 constexpr int kRowsPerBlock = 128;  // 4 waves x 32 rows
 constexpr int kColsPerTile = 128;   // columns staged to LDS per step
@@ -21,8 +25,12 @@ constexpr int kMaxJobs = 4;
 //   L2_i = log2 sum_j 2^{ k * <x_i, y_j> + u_j }    (k = log2(e) / eps)
 // written as (max, sum) partials per column chunk: part[chunk * n_rows + i].
 struct SoftminJob {
-    const float *rows;  // n_rows x KP packed (FP32 path) or bf16 hi/lo planes (split path)
-    const float *cols;  // n_cols x KP packed
+    const float *rows;  // n_rows x KP packed FP32 (centred coordinates)
+    const float *cols;  // FP32 path: n_cols x KP packed
+    const __hip_bfloat16 *cols_hi;  // split path: n_cols x KP, hi part of y_j - c_J
+    const __hip_bfloat16 *cols_lo;  // split path: lo part
+    const int *col_blk_cluster;     // split path: cluster of each 32-column block
+    const float *col_centroids;     // split path: cluster centres, KP floats each
     const float *u;     // n_cols log2-domain column offsets; -inf = no mass
     float2 *part;       // n_chunks x n_rows
     int n_rows, n_cols;
@@ -45,6 +53,33 @@ struct SoftminBatch {
 int plan_softmin_batch(SoftminBatch &b, int target_wgs);
 
 hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
+                          hipStream_t s);
+hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s);
+
+// ---- K-means and the cluster-sorted, 32-padded layout (kmeans.hip) ----
+size_t kmeans_workspace_ints(int n, int k);
+// Lloyd iterations on X (n x kp, centred FP32) with weights w; C: k x kp centres
+// (output), cmass/radius: k (nullable).  *perm_out / *off_out point into ws:
+// perm (sorted position -> point) and off (k + 1 cluster offsets).
+hipError_t run_kmeans(const float *X, const float *w, int n, int kp, int k, int iters, float *C,
+                      float *cmass, float *radius, int *ws, int **perm_out, int **off_out,
+                      hipStream_t s);
+int scan_sums_len(int64_t len);
+hipError_t launch_exclusive_scan(const int *in, int64_t len, int *sums, int *out, hipStream_t s);
+// poff (k + 1): exclusive scan of the cluster sizes rounded up to 32 (psize: k + 1 ints).
+hipError_t build_padded_layout(const int *perm, const int *off, int k, int *psize, int *poff,
+                               int *scan_sums, hipStream_t s);
+hipError_t fill_padded_layout(const int *perm, const int *off, const int *poff, int k,
+                              int *perm_pad, int *blk_cluster, hipStream_t s);
+hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pad,
+                              const int *blk_cluster, const float *C, int n_pad, int kp, float *Xf,
+                              __hip_bfloat16 *Yhi, __hip_bfloat16 *Ylo, float *hn, float *lw,
+                              float *wp, hipStream_t s);
+hipError_t launch_unpack_centres(const float *C, int k, int d, int kp, const float *centre,
+                                 float *out, hipStream_t s);
+hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, float *out,
+                            hipStream_t s);
+hipError_t launch_permute(const float *src, const int *perm_pad, int n_pad, float *out,
                           hipStream_t s);
 
 // Bounding box and validation of one cloud.

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
         if (t < B.n_jobs && wg >= B.job[t].wg_begin) q = t;
-    const float *__restrict__ rows = B.job[q].rows;
+    const float *__restrict__ rows = B.job[q].rows;  // FP32 packed
     const float *__restrict__ cols = B.job[q].cols;
     const float *__restrict__ u = B.job[q].u;
     float2 *__restrict__ part = B.job[q].part;
@@ -185,6 +185,12 @@ int packed_width(int d) {
     int kp = 4;
     while (kp < d + 1) kp *= 2;
     return kp;
+}
+
+int packed_width_bf16(int d) {
+    int kp = 16;
+    while (kp < d + 3) kp *= 2;
+    return kp <= 64 ? kp : 0;
 }
 
 }  // namespace skh

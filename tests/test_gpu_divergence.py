@@ -17,6 +17,7 @@ from gpu_common import cuda, host, note
 pytestmark = pytest.mark.gpu
 
 S_RTOL_FP32 = 1e-5
+S_RTOL_BF16 = 1e-3
 
 
 def _run(x, a, y, b, blur, reach, scaling, extra=0, **kw):
@@ -29,15 +30,16 @@ def _run(x, a, y, b, blur, reach, scaling, extra=0, **kw):
     return S, {k: host(v) for k, v in pot.items()}, st
 
 
-def _compare(x, a, y, b, blur, reach, scaling, extra=0, pot_atol=None):
-    S, pot, st = _run(x, a, y, b, blur, reach, scaling, extra)
+def _compare(x, a, y, b, blur, reach, scaling, extra=0, pot_atol=None, precision="fp32"):
+    S, pot, st = _run(x, a, y, b, blur, reach, scaling, extra, precision=precision)
     Sr, r = oracle.sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling, extra_iters=extra)
     assert st["iters"] == r["iters"] and st["n_scales"] == r["n_scales"]
     assert st["diameter"] == pytest.approx(r["diameter"], rel=1e-12)
-    assert S == pytest.approx(Sr, rel=S_RTOL_FP32), (S, Sr)
+    rtol = S_RTOL_FP32 if precision == "fp32" else S_RTOL_BF16
+    assert S == pytest.approx(Sr, rel=rtol), (S, Sr)
     # potentials: compare after removing the mean (gauge), scale-aware tolerance
     if pot_atol is None:
-        pot_atol = 1e-4 * max(blur ** 2, np.abs(r["f"]).max())
+        pot_atol = (1e-4 if precision == "fp32" else 1e-2) * max(blur ** 2, np.abs(r["f"]).max())
     for k in ("f", "g", "p", "q"):
         dg = pot[k] - r[k]
         dg -= dg.mean() if reach is None else 0.0
@@ -128,3 +130,32 @@ def test_invalid_arguments():
     big = np.zeros((10, 64), np.float32)
     with pytest.raises(skh.SkhError):
         skh.sinkhorn_divergence(cuda(big), cuda(a[:10] * 5), cuda(big), cuda(a[:10] * 5), blur=0.1)
+
+
+# ------------------------------------------------------------- BF16 split ---
+
+def test_fiber_downscaled_bf16_split():
+    x, a, y, b = synth.fiber_pair(3000, 20, seed=7)
+    S, Sr, st = _compare(x, a, y, b, blur=1.0, reach=None, scaling=0.8, precision="bf16x3")
+    print(f"bf16 fibres: S={S:.9g} oracle={Sr:.9g} rel={abs(S - Sr) / abs(Sr):.2e}")
+
+
+def test_fiber_downscaled_bf16_split_unbalanced():
+    x, a, y, b = synth.fiber_pair(2500, 20, seed=9)
+    _compare(x, a, y, b, blur=1.0, reach=20.0, scaling=0.8, extra=3, precision="bf16x3")
+
+
+def test_blob_config_bf16_split():
+    x, a, y, b = synth.blob_pair(2000, seed=0)
+    _compare(x, a, y, b, blur=0.01, reach=None, scaling=0.5, precision="bf16x3")
+
+
+@pytest.mark.parametrize("n,m,d", [(1, 1, 3), (1, 37, 2), (130, 1, 5), (257, 129, 1), (5, 300, 60)])
+def test_edge_sizes_bf16(n, m, d):
+    rng = np.random.default_rng(n + m + d)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    y = (rng.standard_normal((m, d)) + 0.5).astype(np.float32)
+    a = synth.random_weights(n, 1)
+    b = synth.random_weights(m, 2)
+    _compare(x, a, y, b, blur=0.1 * math.sqrt(d), reach=None, scaling=0.6, extra=2,
+             precision="bf16x3")

@@ -91,3 +91,51 @@ def test_softmin_fiber_full_size_sampled_rows():
                                        np.concatenate([ref, np.zeros(len(x))]))[:len(rows)]
         err = np.abs(out[rows] - ref)
         assert np.all(err <= bound_all), (eps, np.max(err / bound_all))
+
+
+# ------------------------------------------------------------- BF16 split ---
+
+def _check_bf16(x, y, w, h, eps, lam, tag):
+    """BF16 hi/lo split: the contraction error of one pair is at most
+    3 * 2^-16 |x_i| |y_j - c_J| (dropped lo.lo product and the two split residuals),
+    with |y_j - c_J| <= 2 max |y| for any cluster centre c_J inside the cloud's hull."""
+    import paper_2107_02010_amd as skh
+    from gpu_common import centred
+    note(f"softmin bf16 {tag} n={x.shape[0]} m={y.shape[0]} d={x.shape[1]} eps={eps}")
+    out = host(skh.softmin(cuda(x), cuda(y), cuda(w), cuda(h), eps, lam, precision="bf16x3"))
+    ref = oracle.softmin(x, y, w, h, eps, lam)
+    xc, yc = centred(x, y)
+    split = 8 * 3 * 2.0 ** -16 * lam * np.linalg.norm(xc, axis=1) * 2 * np.linalg.norm(yc, axis=1).max()
+    bound = softmin_fp32_bound(x, y, w.astype(np.float64), h.astype(np.float64), eps, lam, ref) + split
+    err = np.abs(out - ref)
+    assert np.all(np.isfinite(out))
+    worst = int(np.argmax(err / bound))
+    assert np.all(err <= bound), (tag, worst, out[worst], ref[worst], bound[worst])
+    return err
+
+
+@pytest.mark.parametrize("n,m,d", [(300, 517, 3), (1000, 1300, 60), (257, 4000, 16), (33, 2500, 61),
+                                   (5, 7, 1), (640, 64, 29)])
+@pytest.mark.parametrize("eps_rel", [1e-2, 1.0])
+def test_softmin_bf16_matches_oracle(n, m, d, eps_rel):
+    x, y, w, h = _case(n, m, d, seed=n * 3 + m + d)
+    _check_bf16(x, y, w, h, eps_rel * d, 1.0, "random")
+    _check_bf16(x, y, w, h, eps_rel * d, 0.7, "damped")
+
+
+def test_softmin_bf16_fibres_is_close_to_fp32_accuracy():
+    # clustered fibres: the split error scales with the cluster radius, so the
+    # result is far inside the generic bound
+    x, a, y, b = synth.fiber_pair(6000, 20, seed=3)
+    rng = np.random.default_rng(9)
+    h = (rng.standard_normal(6000)).astype(np.float32)
+    err = _check_bf16(x, y, b, h, 1.0, 1.0, "fibres")
+    assert np.max(err) < 5e-3
+
+
+def test_softmin_bf16_rejects_wide_points():
+    import paper_2107_02010_amd as skh
+    x, y, w, h = _case(10, 10, 62, seed=1)
+    note("softmin bf16 d=62")
+    with pytest.raises(skh.SkhError):
+        skh.softmin(cuda(x), cuda(y), cuda(w), cuda(h), 1.0, precision="bf16x3")
