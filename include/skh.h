@@ -132,6 +132,35 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
                             float *q, skh_stats *stats);
 
 /*
+ * Transport plan of eq. (4) applied to column values:
+ *   out_il = a_i sum_j b_j exp((f_i + g_j - C(x_i, y_j)) / eps) V_jl,
+ * i < n, l < L, V: m x L row-major (device), 1 <= L <= 64.  With
+ * divide_by_a != 0 the a_i factor is left out: for one-hot label vectors V
+ * this is the soft segmentation Lab_i of eq. (7).  f (n) and g (m) are the
+ * dual vectors b^{beta->alpha}, a^{alpha->beta} of a previous solve (FP32,
+ * caller order).  mass (n, nullable) receives the plan's row sums
+ * sum_j pi_ij (a_i left out as for out).  Rows use FP32 arithmetic
+ * throughout (MFMA contraction, online maximum).
+ */
+int skh_plan_apply(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                   const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                   double eps, const float *V, int32_t L, int32_t divide_by_a, float *out,
+                   float *mass);
+
+/*
+ * Gradient of S_{eps,rho}(alpha, beta) with respect to the positions x_i, from
+ * the dual vectors of a converged solve (envelope theorem on eq. (3); the
+ * paper notes the gradients are expressions of the four dual vectors):
+ *   grad_i = sum_j pi_ij (x_i - y_j) - sum_k pi^{aa}_ik (x_i - x_k),
+ * pi from (f, g) and pi^{aa} from (p, p) by eq. (4) at eps = blur^2.
+ * grad: n x d (device, caller order).  Valid for balanced and unbalanced S
+ * (the marginal penalties do not depend on x).
+ */
+int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+               const float *b, int64_t m, int32_t d, const float *f, const float *g,
+               const float *p, double blur, float *grad);
+
+/*
  * K-means coarse scale of one cloud (coarse-to-fine strategy, Section 2: a
  * K-means subsampling of the points for the first, coarse iterations).
  * Lloyd iterations from k evenly strided points (point floor(c n / k) for

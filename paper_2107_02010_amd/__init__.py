@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT  # noqa: F401
 
-__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "SkhError", "library_path"]
+__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x",
+           "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
 
 library_path = _lib.LIB_PATH
 _PREC = {"fp32": _lib.SKH_FP32, "bf16x3": _lib.SKH_BF16_SPLIT, "bf16_split": _lib.SKH_BF16_SPLIT}
@@ -162,3 +163,74 @@ def kmeans(x, w=None, k: int = None, iters: int = 10) -> dict:
                                 _ptr(out["perm"]), _ptr(out["offsets"]))
     _lib.check(rc, ctx)
     return out
+
+
+def plan_apply(x, a, y, b, f, g, eps: float, V, divide_by_a: bool = False,
+               return_mass: bool = False):
+    """(pi V)_i = a_i sum_j b_j exp((f_i + g_j - C(x_i, y_j))/eps) V_j  (eq. (4)); with
+    divide_by_a the a_i factor is dropped (eq. (7) soft labels for one-hot V)."""
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    dev = x.device
+    a, b = _as_vec(a, n, "a", dev), _as_vec(b, m, "b", dev)
+    f, g = _as_vec(f, n, "f", dev), _as_vec(g, m, "g", dev)
+    V = V.to(torch.float32)
+    V = (V.unsqueeze(1) if V.dim() == 1 else V).contiguous()
+    if V.shape[0] != m:
+        raise ValueError("V must have one row per column point")
+    L = V.shape[1]
+    out = torch.empty((n, L), dtype=torch.float32, device=dev)
+    mass = torch.empty(n, dtype=torch.float32, device=dev) if return_mass else None
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_plan_apply(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d, _ptr(f),
+                                    _ptr(g), float(eps), _ptr(V), L, int(bool(divide_by_a)),
+                                    _ptr(out), _ptr(mass))
+    _lib.check(rc, ctx)
+    return (out, mass) if return_mass else out
+
+
+def grad_x(x, a, y, b, f, g, p, blur: float) -> torch.Tensor:
+    """Gradient of S with respect to x from the dual vectors (f, g, p) of a solve:
+    sum_j pi_ij (x_i - y_j) - sum_k pi^aa_ik (x_i - x_k) at eps = blur**2."""
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    dev = x.device
+    a, b = _as_vec(a, n, "a", dev), _as_vec(b, m, "b", dev)
+    f, g, p = _as_vec(f, n, "f", dev), _as_vec(g, m, "g", dev), _as_vec(p, n, "p", dev)
+    out = torch.empty((n, d), dtype=torch.float32, device=dev)
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_grad_x(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d, _ptr(f),
+                                _ptr(g), _ptr(p), float(blur), _ptr(out))
+    _lib.check(rc, ctx)
+    return out
+
+
+class SinkhornDivergence(torch.autograd.Function):
+    """S_eps(alpha, beta) as a differentiable function of the positions x.
+
+    forward runs the solver (eq. (6) after the symmetric loop); backward calls the
+    hand-written gradient kernel with the saved dual vectors, without
+    differentiating through the iterations (envelope theorem at the fixed point).
+    Only x receives a gradient."""
+
+    @staticmethod
+    def forward(ctx, x, a, y, b, kw):
+        S, pot, st = sinkhorn_divergence(x, a, y, b, potentials=True, **kw)
+        ctx.save_for_backward(x, a, y, b, pot["f"], pot["g"], pot["p"])
+        ctx.blur = kw.get("blur", 0.05)
+        return torch.tensor(S, dtype=torch.float64, device=x.device)
+
+    @staticmethod
+    def backward(ctx, gS):
+        x, a, y, b, f, g, p = ctx.saved_tensors
+        gx = None
+        if ctx.needs_input_grad[0]:
+            gx = grad_x(x.detach(), a, y, b, f, g, p, ctx.blur)
+            gx = (gx.to(torch.float64) * gS).to(x.dtype)
+        return gx, None, None, None, None
+
+
+def sinkhorn_loss(x, a, y, b, **kw):
+    """Differentiable S_eps (see SinkhornDivergence); kw as for sinkhorn_divergence."""
+    kw.pop("potentials", None)
+    return SinkhornDivergence.apply(x, a, y, b, kw)

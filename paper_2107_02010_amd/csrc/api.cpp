@@ -7,6 +7,7 @@
 // offsets.  The host synchronises only for the bounding box (scale list and
 // validation), for the periodic marginal-error check in converged mode, and
 // for the final FP64 value of eq. (6).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -686,6 +687,151 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     }
     if (!std::isfinite(S)) return fail(ctx, SKH_ENONFINITE, "non-finite divergence");
     if (P.tol > 0.0 && !converged) return SKH_NOT_CONVERGED;
+    return SKH_OK;
+}
+
+namespace {
+
+// Shared body of skh_plan_apply and skh_grad_x: up to two plan jobs over the
+// same row cloud x, each against its own column cloud, potentials and values.
+struct PlanSpec {
+    const float *cols;    // caller points (m x d)
+    const float *cw;      // column weights
+    int64_t m;
+    const float *fpot;    // row potential
+    const float *gpot;    // column potential
+    const float *V;       // values (m x L) or NULL: column coordinates
+    int L;
+    float *out;           // n x L
+    float *mass;          // n or NULL
+};
+
+int run_plans(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d, double eps,
+              int divide_by_a, const PlanSpec *specs, int nspec, float **Xp_out, int *kp_out,
+              hipStream_t s) {
+    const int kp = skh::packed_width(d);
+    int Lmax = 1;
+    for (int k = 0; k < nspec; ++k) Lmax = std::max(Lmax, specs[k].L);
+    const int lp = skh::plan_value_width(Lmax);
+    if (!lp) return fail(ctx, SKH_EINVAL, "L must be <= 64");
+    int nb[3] = {skh::bbox_blocks(n), 0, 0};
+    for (int k = 0; k < nspec; ++k) nb[1 + k] = skh::bbox_blocks(specs[k].m);
+    const int nbt = nb[0] + nb[1] + nb[2];
+    skh::PlanBatch batch{};
+    batch.n_jobs = nspec;
+    batch.d = d;
+    batch.kscale = (float)(kLog2e / eps);
+    for (int k = 0; k < nspec; ++k) {
+        batch.job[k].n_rows = (int)n;
+        batch.job[k].n_cols = (int)specs[k].m;
+        batch.job[k].L = specs[k].L;
+    }
+    const int wgs = skh::plan_plan_batch(batch, target_wgs(ctx));
+    float *Xp, *hnx, *plo, *phi, *lohi, *Cp[2], *hnc[2], *lwc[2], *uc[2], *part[2];
+    double *pmass, *mass;
+    int *pbad, *bad;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[0] : nullptr);
+        Xp = c.take<float>((size_t)n * kp);
+        hnx = c.take<float>(n);
+        for (int k = 0; k < nspec; ++k) {
+            Cp[k] = c.take<float>((size_t)specs[k].m * kp);
+            hnc[k] = c.take<float>(specs[k].m);
+            lwc[k] = c.take<float>(specs[k].m);
+            uc[k] = c.take<float>(specs[k].m);
+            part[k] = c.take<float>((size_t)batch.job[k].n_chunks * n * (specs[k].L + 2));
+        }
+        plo = c.take<float>((size_t)nbt * 64);
+        phi = c.take<float>((size_t)nbt * 64);
+        pmass = c.take<double>(nbt);
+        pbad = c.take<int>(2 * nbt);
+        lohi = c.take<float>(192);
+        mass = c.take<double>(2);
+        bad = c.take<int>(4);
+        if (!pass) {
+            int rc = ensure_ws(ctx, 0, c.off);
+            if (rc) return rc;
+        }
+    }
+    // common centre: bounding box of x and every column cloud
+    SKH_HIP(skh::launch_bbox_partial(x, nullptr, n, d, plo, phi, pmass, pbad, s));
+    int off = nb[0];
+    for (int k = 0; k < nspec; ++k) {
+        SKH_HIP(skh::launch_bbox_partial(specs[k].cols, nullptr, specs[k].m, d, plo + (size_t)off * 64,
+                                         phi + (size_t)off * 64, pmass + off, pbad + 2 * off, s));
+        off += nb[1 + k];
+    }
+    SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nb[0], nbt - nb[0], d, lohi, mass, bad, s));
+    SKH_HIP(skh::launch_pack(x, nullptr, n, d, kp, lohi + 128, Xp, hnx, nullptr, s));
+    for (int k = 0; k < nspec; ++k) {
+        const PlanSpec &P = specs[k];
+        SKH_HIP(skh::launch_pack(P.cols, P.cw, P.m, d, kp, lohi + 128, Cp[k], hnc[k], lwc[k], s));
+        SKH_HIP(skh::launch_col_offsets(lwc[k], P.gpot, hnc[k], P.m, eps, uc[k], s));
+        skh::PlanJob &J = batch.job[k];
+        J.rows = Xp;
+        J.cols = Cp[k];
+        J.u = uc[k];
+        J.V = P.V;
+        J.part = part[k];
+    }
+    SKH_HIP(skh::launch_plan_weighted(batch, kp, lp, wgs, s));
+    for (int k = 0; k < nspec; ++k) {
+        const PlanSpec &P = specs[k];
+        SKH_HIP(skh::launch_plan_finish(part[k], batch.job[k].n_chunks, (int)n, P.L, hnx, P.fpot,
+                                        divide_by_a ? nullptr : a, eps, P.out, P.mass, s));
+    }
+    if (Xp_out) *Xp_out = Xp;
+    if (kp_out) *kp_out = kp;
+    return SKH_OK;
+}
+
+}  // namespace
+
+int skh_plan_apply(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                   const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                   double eps, const float *V, int32_t L, int32_t divide_by_a, float *out,
+                   float *mass) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !a || !y || !b || !f || !g || !V || !out)
+        return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
+        return fail(ctx, SKH_EINVAL, "n, m out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    if (L < 1 || L > 64) return fail(ctx, SKH_EINVAL, "L must be in [1, 64]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ctx, SKH_EINVAL, "eps must be > 0");
+    DeviceGuard guard(ctx->device);
+    PlanSpec sp{y, b, m, f, g, V, L, out, mass};
+    return run_plans(ctx, x, a, n, d, eps, divide_by_a, &sp, 1, nullptr, nullptr, ctx->stream);
+}
+
+int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+               const float *b, int64_t m, int32_t d, const float *f, const float *g,
+               const float *p, double blur, float *grad) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !a || !y || !b || !f || !g || !p || !grad)
+        return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
+        return fail(ctx, SKH_EINVAL, "n, m out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    if (!(blur > 0.0) || !std::isfinite(blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = ctx->stream;
+    // value buffers in the loop workspace: P1, m1, P2, m2
+    float *buf;
+    const size_t words = (size_t)n * d * 2 + (size_t)n * 2;
+    {
+        int rc = ensure_ws(ctx, 1, words * sizeof(float) + 1024);
+        if (rc) return rc;
+        buf = static_cast<float *>(ctx->ws[1]);
+    }
+    float *P1 = buf, *P2 = P1 + (size_t)n * d, *m1 = P2 + (size_t)n * d, *m2 = m1 + n;
+    const double eps = blur * blur;
+    PlanSpec sp[2] = {{y, b, m, f, g, nullptr, d, P1, m1}, {x, a, n, p, p, nullptr, d, P2, m2}};
+    float *Xp = nullptr;
+    int kp = 0;
+    int rc = run_plans(ctx, x, a, n, d, eps, 0, sp, 2, &Xp, &kp, s);
+    if (rc) return rc;
+    SKH_HIP(skh::launch_grad_combine(Xp, (int)n, d, kp, P1, m1, P2, m2, grad, s));
     return SKH_OK;
 }
 

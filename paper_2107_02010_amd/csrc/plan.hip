@@ -1,0 +1,284 @@
+// Transport plan applied to column values, and the weighted sums behind the
+// gradient of S with respect to x.
+//
+// With the dual vectors (f, g) the plan is pi_ij = a_i b_j exp((f_i + g_j - C_ij)/eps)
+// (eq. (4)).  For a row i and column values V_j (L of them) the kernel computes
+//
+//   W_i = sum_j 2^{s_ij - M_i},   P_il = sum_j 2^{s_ij - M_i} V_jl,
+//   s_ij = k <x_i, y_j> + u_j,    u_j = log2(e) (log b_j + (g_j - |y_j|^2/2) / eps),
+//
+// with the running maximum M_i kept online exactly as in the softmin kernel,
+// so that
+//   sum_j pi_ij V_jl = a_i 2^{log2(e) (f_i - |x_i|^2/2) / eps + M_i} P_il.
+//
+// V is either a caller matrix (m x L, staged in LDS) or, for the gradient,
+// the centred column coordinates themselves (L = d, read from the tile).
+// s_ij comes from v_mfma_f32_32x32x2f32 as in the softmin; the accumulator
+// layout of that instruction gives lane l (row i = l % 32) the columns
+// j = 8 (r / 4) + 4 (l / 32) + (r % 4) of its 16 registers r, which is how
+// each lane finds the V rows to weight.
+#include "skh_internal.h"
+
+namespace skh {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+static __device__ __forceinline__ float ninf() { return -__builtin_huge_valf(); }
+static __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <int KP, int LP>
+__global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
+    constexpr int H = KP / 2;
+    constexpr int STRIDE = KP + 4;
+    constexpr int V4 = KP / 4;
+    constexpr int VSTRIDE = LP + 4;
+    __shared__ __attribute__((aligned(16))) float tile[kColsPerTile * STRIDE];
+    __shared__ __attribute__((aligned(16))) float vtile[kColsPerTile * VSTRIDE];
+
+    const int wg = blockIdx.x;
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < kMaxJobs; ++t)
+        if (t < B.n_jobs && wg >= B.job[t].wg_begin) q = t;
+    const PlanJob &J = B.job[q];
+    const float *__restrict__ rows = J.rows;
+    const float *__restrict__ cols = J.cols;
+    const float *__restrict__ u = J.u;
+    const float *__restrict__ V = J.V;
+    float *__restrict__ part = J.part;
+    const int n_rows = J.n_rows, n_cols = J.n_cols, L = J.L;
+    const int row_tiles = J.row_tiles, chunk_cols = J.chunk_cols;
+    const int local = wg - J.wg_begin;
+    const int rt = local % row_tiles, chunk = local / row_tiles;
+    const int d = B.d;
+    const float kscale = B.kscale;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, li = lane & 31;
+    const int i = rt * kRowsPerBlock + wave * 32 + li;
+    const int ic = i < n_rows ? i : n_rows - 1;
+
+    float xr[H];
+    {
+        const float *rp = rows + (size_t)ic * KP + h * H;
+#pragma unroll
+        for (int s = 0; s < H; ++s) xr[s] = rp[s];
+#pragma unroll
+        for (int s = 0; s < H; ++s) xr[s] = (h * H + s == d) ? 1.0f : xr[s] * kscale;
+    }
+
+    const int c_begin = chunk * chunk_cols;
+    const int c_end = min(n_cols, c_begin + chunk_cols);
+    float m = ninf(), wsum = 0.0f;
+    float vacc[LP];
+#pragma unroll
+    for (int l = 0; l < LP; ++l) vacc[l] = 0.0f;
+
+    for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
+        __syncthreads();
+        for (int e = tid; e < kColsPerTile * V4; e += 256) {
+            const int c = e / V4, v = e - c * V4;
+            const int j = j0 + c;
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < c_end) val = *reinterpret_cast<const float4 *>(cols + (size_t)j * KP + v * 4);
+            *reinterpret_cast<float4 *>(&tile[c * STRIDE + v * 4]) = val;
+        }
+        for (int e = tid; e < kColsPerTile * LP; e += 256) {
+            const int c = e / LP, l = e - c * LP;
+            const int j = j0 + c;
+            float val = 0.0f;
+            if (j < c_end && l < L) val = V ? V[(size_t)j * L + l] : cols[(size_t)j * KP + l];
+            vtile[c * VSTRIDE + l] = val;
+        }
+        __syncthreads();
+        if (tid < kColsPerTile) {  // augmented coordinate: the column offset
+            const int j = j0 + tid;
+            tile[tid * STRIDE + d] = j < c_end ? u[j] : ninf();
+        }
+        __syncthreads();
+        const int nblk = min(kColsPerTile / 32, (c_end - j0 + 31) >> 5);
+        for (int jb = 0; jb < nblk; ++jb) {
+            v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                        0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float *tp = &tile[(jb * 32 + li) * STRIDE + h * H];
+#pragma unroll
+            for (int s = 0; s < H; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[s], xr[s], acc, 0, 0, 0);
+            float tmax = acc[0];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
+            const float mn = fmaxf(m, tmax);
+            if (mn > ninf()) {
+                const float sc = fast_exp2(m - mn);
+                wsum *= sc;
+#pragma unroll
+                for (int l = 0; l < LP; ++l) vacc[l] *= sc;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float w = fast_exp2(acc[r] - mn);
+                    wsum += w;
+                    const int jl = jb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const float *vr = &vtile[jl * VSTRIDE];
+#pragma unroll
+                    for (int l = 0; l < LP; l += 4) {
+                        const float4 vv = *reinterpret_cast<const float4 *>(vr + l);
+                        vacc[l] = fmaf(w, vv.x, vacc[l]);
+                        if (l + 1 < LP) vacc[l + 1] = fmaf(w, vv.y, vacc[l + 1]);
+                        if (l + 2 < LP) vacc[l + 2] = fmaf(w, vv.z, vacc[l + 2]);
+                        if (l + 3 < LP) vacc[l + 3] = fmaf(w, vv.w, vacc[l + 3]);
+                    }
+                }
+                m = mn;
+            }
+        }
+    }
+
+    // merge the two lane halves of each row
+    const float m2 = __shfl_xor(m, 32, 64);
+    const float M = fmaxf(m, m2);
+    const float s1 = M > ninf() ? fast_exp2(m - M) : 0.0f;
+    const float s2 = M > ninf() ? fast_exp2(m2 - M) : 0.0f;
+    const float w2 = __shfl_xor(wsum, 32, 64);
+    const float W = wsum * s1 + w2 * s2;
+    // partial record: [M, W, P_0 .. P_{L-1}]
+    const int RW = L + 2;
+    float *rec = part + ((size_t)chunk * n_rows + i) * RW;
+#pragma unroll
+    for (int l = 0; l < LP; ++l) {
+        const float o = __shfl_xor(vacc[l], 32, 64);
+        const float val = vacc[l] * s1 + o * s2;
+        if (h == 0 && i < n_rows && l < L) rec[2 + l] = val;
+    }
+    if (h == 0 && i < n_rows) {
+        rec[0] = M;
+        rec[1] = W;
+    }
+}
+
+int plan_plan_batch(PlanBatch &b, int target_wgs) {
+    int row_tiles_total = 0;
+    for (int q = 0; q < b.n_jobs; ++q) {
+        PlanJob &J = b.job[q];
+        J.row_tiles = (J.n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
+        row_tiles_total += J.row_tiles;
+    }
+    int want_chunks = row_tiles_total > 0 ? (target_wgs + row_tiles_total - 1) / row_tiles_total : 1;
+    if (want_chunks < 1) want_chunks = 1;
+    int total = 0;
+    for (int q = 0; q < b.n_jobs; ++q) {
+        PlanJob &J = b.job[q];
+        const int tiles = (J.n_cols + kColsPerTile - 1) / kColsPerTile;
+        int per = (tiles + want_chunks - 1) / want_chunks;
+        if (per < 1) per = 1;
+        J.chunk_cols = per * kColsPerTile;
+        J.n_chunks = (J.n_cols + J.chunk_cols - 1) / J.chunk_cols;
+        if (J.n_chunks < 1) J.n_chunks = 1;
+        J.wg_begin = total;
+        total += J.row_tiles * J.n_chunks;
+    }
+    return total;
+}
+
+int plan_value_width(int L) {
+    int lp = 4;
+    while (lp < L) lp *= 2;
+    return lp <= 64 ? lp : 0;
+}
+
+template <int KP>
+static hipError_t launch_kp(const PlanBatch &b, int lp, dim3 grid, hipStream_t s) {
+    switch (lp) {
+    case 4: hipLaunchKernelGGL((k_plan_weighted<KP, 4>), grid, dim3(256), 0, s, b); break;
+    case 8: hipLaunchKernelGGL((k_plan_weighted<KP, 8>), grid, dim3(256), 0, s, b); break;
+    case 16: hipLaunchKernelGGL((k_plan_weighted<KP, 16>), grid, dim3(256), 0, s, b); break;
+    case 32: hipLaunchKernelGGL((k_plan_weighted<KP, 32>), grid, dim3(256), 0, s, b); break;
+    case 64: hipLaunchKernelGGL((k_plan_weighted<KP, 64>), grid, dim3(256), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_weighted(const PlanBatch &b, int kp, int lp, int total_wgs, hipStream_t s) {
+    dim3 grid(total_wgs);
+    switch (kp) {
+    case 4: return launch_kp<4>(b, lp, grid, s);
+    case 8: return launch_kp<8>(b, lp, grid, s);
+    case 16: return launch_kp<16>(b, lp, grid, s);
+    case 32: return launch_kp<32>(b, lp, grid, s);
+    case 64: return launch_kp<64>(b, lp, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Merges chunk records [M, W, P_0..P_{L-1}] of one job into
+//   out_il = scale_i 2^{c_i + M_i} P_il,  c_i = log2(e) (pot_i - hn_i) / eps,
+// scale_i = w_i (or 1), and mass_i = scale_i 2^{c_i + M_i} W_i when mass != NULL.
+__global__ __launch_bounds__(256) void k_plan_finish(const float *__restrict__ part, int chunks,
+                                                     int n, int L, const float *__restrict__ hn,
+                                                     const float *__restrict__ pot,
+                                                     const float *__restrict__ w, double eps,
+                                                     float *__restrict__ out,
+                                                     float *__restrict__ mass) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int RW = L + 2;
+    float M = ninf();
+    for (int c = 0; c < chunks; ++c) M = fmaxf(M, part[((size_t)c * n + i) * RW]);
+    const double scale = w ? (double)w[i] : 1.0;
+    double base = 0.0;
+    if (M > ninf())
+        base = scale * exp2(1.4426950408889634074 * ((double)pot[i] - (double)hn[i]) / eps + (double)M);
+    double W = 0.0;
+    for (int l = 0; l < L; ++l) {
+        double acc = 0.0;
+        for (int c = 0; c < chunks; ++c) {
+            const float *rec = part + ((size_t)c * n + i) * RW;
+            if (rec[0] > ninf()) acc += (double)rec[2 + l] * exp2((double)rec[0] - (double)M);
+        }
+        out[(size_t)i * L + l] = (float)(base * acc);
+    }
+    if (mass) {
+        for (int c = 0; c < chunks; ++c) {
+            const float *rec = part + ((size_t)c * n + i) * RW;
+            if (rec[0] > ninf()) W += (double)rec[1] * exp2((double)rec[0] - (double)M);
+        }
+        mass[i] = (float)(base * W);
+    }
+}
+
+hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const float *hn,
+                              const float *pot, const float *w, double eps, float *out,
+                              float *mass, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_finish, dim3((n + 255) / 256), dim3(256), 0, s, part, chunks, n, L, hn,
+                       pot, w, eps, out, mass);
+    return hipGetLastError();
+}
+
+// grad_i = (m1_i x_i - P1_i) - (m2_i x_i - P2_i), x centred (packed, stride kp);
+// P1 = sum_j pi_ij y_j, m1 = sum_j pi_ij, P2 = sum_k pi^aa_ik x_k, m2 = sum_k pi^aa_ik.
+__global__ __launch_bounds__(256) void k_grad_combine(const float *__restrict__ X, int n, int d,
+                                                      int kp, const float *__restrict__ P1,
+                                                      const float *__restrict__ m1,
+                                                      const float *__restrict__ P2,
+                                                      const float *__restrict__ m2,
+                                                      float *__restrict__ grad) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * d) return;
+    const int i = e / d, t = e % d;
+    const double x = X[(size_t)i * kp + t];
+    const double g1 = (double)m1[i] * x - (double)P1[e];
+    const double g2 = (double)m2[i] * x - (double)P2[e];
+    grad[e] = (float)(g1 - g2);
+}
+
+hipError_t launch_grad_combine(const float *X, int n, int d, int kp, const float *P1,
+                               const float *m1, const float *P2, const float *m2, float *grad,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)(((int64_t)n * d + 255) / 256)), dim3(256), 0,
+                       s, X, n, d, kp, P1, m1, P2, m2, grad);
+    return hipGetLastError();
+}
+
+}  // namespace skh

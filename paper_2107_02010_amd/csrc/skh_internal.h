@@ -56,6 +56,33 @@ hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int tota
                           hipStream_t s);
 hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s);
 
+// ---- Plan applied to column values (plan.hip) ----
+struct PlanJob {
+    const float *rows;  // n_rows x KP packed FP32
+    const float *cols;  // n_cols x KP packed FP32
+    const float *u;     // n_cols column offsets (as in SoftminJob)
+    const float *V;     // n_cols x L values, or NULL: the centred column coordinates (L = d)
+    float *part;        // n_chunks x n_rows records [M, W, P_0 .. P_{L-1}]
+    int n_rows, n_cols, L;
+    int row_tiles, n_chunks, chunk_cols, wg_begin;
+};
+struct PlanBatch {
+    PlanJob job[kMaxJobs];
+    int n_jobs;
+    int d;
+    float kscale;
+    int pad;
+};
+int plan_plan_batch(PlanBatch &b, int target_wgs);
+int plan_value_width(int L);  // 4..64, 0 if L > 64
+hipError_t launch_plan_weighted(const PlanBatch &b, int kp, int lp, int total_wgs, hipStream_t s);
+hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const float *hn,
+                              const float *pot, const float *w, double eps, float *out,
+                              float *mass, hipStream_t s);
+hipError_t launch_grad_combine(const float *X, int n, int d, int kp, const float *P1,
+                               const float *m1, const float *P2, const float *m2, float *grad,
+                               hipStream_t s);
+
 // ---- K-means and the cluster-sorted, 32-padded layout (kmeans.hip) ----
 size_t kmeans_workspace_ints(int n, int k);
 // Lloyd iterations on X (n x kp, centred FP32) with weights w; C: k x kp centres

@@ -11,6 +11,9 @@ the IFOF track-density maps).
                   spines with per-fibre control-point jitter, resampled to P
                   points at equal arc length and flattened to P*3 features
                   scaled by 1/sqrt(P) (the paper's fibre encoding, Section 2).
+* ``density_maps``  track-density-like volumes: sums of Gaussian tubes along
+                  jittered Bezier spines on a voxel grid, kept to the densest
+                  voxels, returned as weighted voxel centres.
 * ``uniform_weights``  1/N weights.
 """
 from __future__ import annotations
@@ -123,3 +126,62 @@ def random_weights(n: int, seed: int, total: float = 1.0, zero_frac: float = 0.0
 def random_cloud(n: int, d: int, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return (scale * rng.standard_normal((n, d))).astype(np.float32)
+
+
+def density_maps(K: int, seed: int, grid: int = 128, n_tubes: int = 8, jitter: float = 3.0,
+                 nonzero=(250_000, 350_000), sigma=(2.0, 4.0), samples_per_voxel: float = 16.0):
+    """K track-density maps on a grid^3 voxel grid (voxel = 1 unit).
+
+    Template spines (cubic Bezier, control points ~ U[0.05 grid, 0.95 grid]^3) are
+    shared; map k jitters every control point by N(0, jitter^2) and gives each tube a
+    cross-section sigma ~ U[sigma].  Density = histogram of points drawn uniformly
+    along each spine parameter plus an isotropic N(0, sigma^2) offset (a Gaussian
+    tube).  Map k keeps its N_k ~ U[nonzero] densest voxels (fewer if fewer are
+    nonzero); weights = density / sum.  Returns a list of (centres (N_k, 3) FP32
+    at voxel centres, weights (N_k,) FP32).
+    """
+    rng = np.random.default_rng(seed)
+    lo, hi = 0.05 * grid, 0.95 * grid
+    spines = rng.uniform(lo, hi, size=(n_tubes, 4, 3))
+    maps = []
+    for k in range(K):
+        ctrl = spines + jitter * rng.standard_normal(spines.shape)
+        sig = rng.uniform(sigma[0], sigma[1], size=n_tubes)
+        target = int(rng.integers(nonzero[0], nonzero[1] + 1))
+        n_samp = int(samples_per_voxel * target)
+        tube = rng.integers(0, n_tubes, size=n_samp)
+        t = rng.uniform(0.0, 1.0, size=n_samp)
+        s = 1.0 - t
+        basis = np.stack([s ** 3, 3 * s * s * t, 3 * s * t * t, t ** 3], axis=1)
+        pts = np.einsum("nk,nkc->nc", basis, ctrl[tube])
+        pts += sig[tube][:, None] * rng.standard_normal((n_samp, 3))
+        idx = np.floor(pts).astype(np.int64)
+        ok = np.all((idx >= 0) & (idx < grid), axis=1)
+        flat = (idx[ok, 0] * grid + idx[ok, 1]) * grid + idx[ok, 2]
+        counts = np.bincount(flat, minlength=grid ** 3)
+        nz = np.flatnonzero(counts)
+        keep = nz[np.argsort(-counts[nz], kind="stable")[:target]]
+        keep.sort()
+        cz = keep % grid
+        cy = (keep // grid) % grid
+        cx = keep // (grid * grid)
+        centres = np.stack([cx, cy, cz], axis=1).astype(np.float64) + 0.5
+        w = counts[keep].astype(np.float64)
+        maps.append((centres.astype(np.float32), (w / w.sum()).astype(np.float32)))
+    return maps
+
+
+def barycenter_support(maps, n: int, seed: int):
+    """n support points drawn from the average of the maps (each map equally likely,
+    then a voxel by its weight), jittered uniformly inside the voxel; weights 1/n."""
+    rng = np.random.default_rng(seed)
+    which = rng.integers(0, len(maps), size=n)
+    out = np.empty((n, 3))
+    for k, (c, w) in enumerate(maps):
+        sel = np.flatnonzero(which == k)
+        if len(sel) == 0:
+            continue
+        p = w.astype(np.float64)
+        vox = rng.choice(len(c), size=len(sel), p=p / p.sum())
+        out[sel] = c[vox].astype(np.float64) + rng.uniform(-0.5, 0.5, size=(len(sel), 3))
+    return out.astype(np.float32), uniform_weights(n)
