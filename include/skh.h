@@ -60,13 +60,20 @@ typedef struct skh_params {
     double scaling;      /* ratio q of consecutive scales, in (0, 1); the paper's default is 0.9 */
     double diameter;     /* largest scale; <= 0: diagonal of the joint bounding box of x and y */
     double tol;          /* > 0: converged mode, iterate at blur until the marginal error <= tol */
+    double jump_scale;   /* multiscale: the fine phase starts at the first sigma <= jump_scale;
+                            0: the mass-weighted RMS cluster radius; < 0: no coarse phase */
+    double trunc_theta;  /* multiscale: keep cluster blocks whose weight bound is >= e^{-theta};
+                            <= 0: keep every block */
     int32_t extra_iters; /* iterations at sigma = blur after the scale list (>= 0) */
     int32_t max_iters;   /* converged mode: at most this many iterations after the list */
     int32_t check_every; /* converged mode: marginal-error check period (>= 1) */
     int32_t precision;   /* SKH_FP32 or SKH_BF16_SPLIT */
     int32_t init;        /* nonzero: f, g, p, q hold starting values (warm start) */
     int32_t timing;      /* nonzero: time every softmin launch with HIP events (skh_stats) */
-    int32_t reserved[6]; /* must be zero */
+    int32_t multiscale;  /* nonzero: K-means coarse phase + cluster-block truncation */
+    int32_t n_clusters;  /* multiscale / split path: clusters per cloud; 0: ceil(sqrt(n)) */
+    int32_t kmeans_iters;/* Lloyd iterations (>= 0) */
+    int32_t reserved[5]; /* must be zero */
 } skh_params;
 
 /* Run statistics. */
@@ -76,19 +83,23 @@ typedef struct skh_stats {
     int32_t converged;   /* converged mode: tolerance met */
     int32_t checks;      /* number of marginal-error checks (each one host sync) */
     int32_t softmin_launches; /* softmin kernel launches (one per iteration) */
-    int32_t reserved_i[3];
+    int32_t coarse_iters;/* multiscale: iterations on the coarse (K-means) clouds */
+    int32_t reserved_i[2];
     double diameter;     /* largest scale used */
     double eps;          /* eps of the last iteration */
     double marginal_err; /* last measured relative L1 marginal error (max of the four problems) */
-    double pairs;        /* point pairs evaluated by the softmin kernels */
+    double pairs;        /* point pairs evaluated by the softmin kernels (kept blocks only) */
     double ms_total;     /* wall time of the call, ms (host clock, inputs resident) */
     double ms_softmin;   /* params.timing: summed device time of the softmin launches, ms */
-    double reserved[2];
+    double dense_pairs;  /* pairs a dense solve with the same iterations would evaluate */
+    double reserved[1];
 } skh_stats;
 
 /* Fills *p with blur = 0.05, reach = +inf (balanced), scaling = 0.9,
  * diameter = 0 (auto), tol = 0 (schedule mode), extra_iters = 0,
- * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0. */
+ * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0,
+ * multiscale = 0, jump_scale = 0, trunc_theta = 20, n_clusters = 0,
+ * kmeans_iters = 10. */
 void skh_params_default(skh_params *p);
 
 /* Creates a context on HIP device `device` bound to stream `hip_stream`

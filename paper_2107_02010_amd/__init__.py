@@ -92,7 +92,9 @@ def softmin(x, y, w, h, eps: float, lam: float = 1.0, precision: str = "fp32") -
 def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: float = 0.9,
                         diameter=None, extra_iters: int = 0, tol: float = 0.0,
                         max_iters: int = 1000, check_every: int = 5, precision: str = "fp32",
-                        init=None, potentials: bool = False, timing: bool = False):
+                        init=None, potentials: bool = False, timing: bool = False,
+                        multiscale: bool = False, jump_scale: float = 0.0,
+                        trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10):
     """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
 
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
@@ -100,6 +102,8 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     init: optional (f, g, p, q) starting potentials.  With potentials=True returns
     (S, dict(f=..., g=..., p=..., q=...), stats dict), else S (a Python float).
     timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
+    multiscale=True: K-means coarse phase while sigma > jump_scale (0: RMS cluster radius,
+    < 0: none), then cluster-block truncation at weight e^{-trunc_theta} (<= 0: none).
     """
     x, y = _as_points(x, "x"), _as_points(y, "y")
     if x.shape[1] != y.shape[1]:
@@ -118,6 +122,11 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     P.check_every = int(check_every)
     P.precision = _PREC[precision]
     P.timing = 1 if timing else 0
+    P.multiscale = 1 if multiscale else 0
+    P.jump_scale = float(jump_scale)
+    P.trunc_theta = float(trunc_theta)
+    P.n_clusters = int(n_clusters)
+    P.kmeans_iters = int(kmeans_iters)
     dev = x.device
     if init is not None:
         f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in

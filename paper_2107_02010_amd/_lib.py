@@ -29,17 +29,19 @@ _c_i32, _c_i64, _c_d, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, c
 class SkhParams(ctypes.Structure):
     _fields_ = [
         ("blur", _c_d), ("reach", _c_d), ("scaling", _c_d), ("diameter", _c_d), ("tol", _c_d),
+        ("jump_scale", _c_d), ("trunc_theta", _c_d),
         ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
-        ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("reserved", _c_i32 * 6),
+        ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("multiscale", _c_i32),
+        ("n_clusters", _c_i32), ("kmeans_iters", _c_i32), ("reserved", _c_i32 * 5),
     ]
 
 
 class SkhStats(ctypes.Structure):
     _fields_ = [
         ("iters", _c_i32), ("n_scales", _c_i32), ("converged", _c_i32), ("checks", _c_i32),
-        ("softmin_launches", _c_i32), ("reserved_i", _c_i32 * 3),
+        ("softmin_launches", _c_i32), ("coarse_iters", _c_i32), ("reserved_i", _c_i32 * 2),
         ("diameter", _c_d), ("eps", _c_d), ("marginal_err", _c_d), ("pairs", _c_d),
-        ("ms_total", _c_d), ("ms_softmin", _c_d), ("reserved", _c_d * 2),
+        ("ms_total", _c_d), ("ms_softmin", _c_d), ("dense_pairs", _c_d), ("reserved", _c_d * 1),
     ]
 
     def as_dict(self):

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libskh.so")
 
-SOURCES = ["softmin.hip", "softmin_bf16.hip", "plan.hip", "kmeans.hip", "aux_kernels.hip", "api.cpp"]
+SOURCES = ["softmin.hip", "softmin_bf16.hip", "plan.hip", "kmeans.hip", "multiscale.hip",
+           "aux_kernels.hip", "api.cpp"]
 ARCH = os.environ.get("SKH_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code; hipcc's host

@@ -128,6 +128,7 @@ int ensure_events(skh_ctx *ctx, size_t count) {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr int64_t kMaxPoints = 1 << 28;
 constexpr int kKmeansIters = 10;
+constexpr int kRowTile = skh::kRowsPerBlock;
 
 // Number of K-means clusters for n points: ceil(sqrt(n)), at most 4096.
 int kmeans_k(int64_t n) {
@@ -139,27 +140,38 @@ int kmeans_k(int64_t n) {
 
 // Device buffers of one cloud in the cluster-sorted, 32-padded layout.
 struct Clustered {
-    int n = 0, k = 0, n_pad_max = 0, n_pad = 0;
+    int n = 0, k = 0, n_pad_max = 0, n_pad = 0, max_tiles = 0, n_tiles = 0;
     float *C = nullptr, *cmass = nullptr, *radius = nullptr;  // k x kp, k, k
+    float *hnC = nullptr, *lwC = nullptr;                     // coarse measure: k, k
     int *kws = nullptr;                                       // K-means workspace
     int *psize = nullptr, *poff = nullptr, *ssum = nullptr;   // k + 1, k + 1, scan sums
+    int *tcnt = nullptr, *toff = nullptr;                     // k + 1 each (row tiles)
+    int4 *tiles = nullptr;                                    // max_tiles
     int *perm_pad = nullptr, *blk = nullptr;                  // n_pad_max, n_pad_max / 32
     float *Xf = nullptr;                                      // n_pad_max x kp
     __hip_bfloat16 *Yhi = nullptr, *Ylo = nullptr;            // n_pad_max x kp
     float *hn = nullptr, *lw = nullptr, *wp = nullptr;        // n_pad_max
     int *perm = nullptr, *off = nullptr;                      // inside kws, set by K-means
+    std::vector<int> h_poff;                                  // host copies
+    std::vector<float> h_mass, h_rad;
 
-    void carve(Carver &c, int n_, int kp) {
+    void carve(Carver &c, int n_, int kp, int k_req) {
         n = n_;
-        k = kmeans_k(n_);
+        k = k_req > 0 ? std::min(std::min(k_req, n_), 4096) : kmeans_k(n_);
         n_pad_max = n_ + 31 * k;
+        max_tiles = n_pad_max / kRowTile + k + 1;
         C = c.take<float>((size_t)k * kp);
         cmass = c.take<float>(k);
         radius = c.take<float>(k);
+        hnC = c.take<float>(k);
+        lwC = c.take<float>(k);
         kws = c.take<int>(skh::kmeans_workspace_ints(n_, k));
         psize = c.take<int>(k + 1);
         poff = c.take<int>(k + 1);
         ssum = c.take<int>(skh::scan_sums_len(k + 1));
+        tcnt = c.take<int>(k + 1);
+        toff = c.take<int>(k + 1);
+        tiles = c.take<int4>(max_tiles);
         perm_pad = c.take<int>(n_pad_max);
         blk = c.take<int>(n_pad_max / 32 + 1);
         Xf = c.take<float>((size_t)n_pad_max * kp);
@@ -172,9 +184,9 @@ struct Clustered {
 };
 
 // K-means of a packed cloud and the padded cluster sizes (poff[k] = n_pad).
-int cluster_start(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, int kp,
+int cluster_start(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, int kp, int iters,
                   hipStream_t s) {
-    SKH_HIP(skh::run_kmeans(X, w, cl.n, kp, cl.k, kKmeansIters, cl.C, cl.cmass, cl.radius, cl.kws,
+    SKH_HIP(skh::run_kmeans(X, w, cl.n, kp, cl.k, iters, cl.C, cl.cmass, cl.radius, cl.kws,
                             &cl.perm, &cl.off, s));
     SKH_HIP(skh::build_padded_layout(cl.perm, cl.off, cl.k, cl.psize, cl.poff, cl.ssum, s));
     return SKH_OK;
@@ -209,6 +221,11 @@ void skh_params_default(skh_params *p) {
     p->precision = SKH_FP32;
     p->init = 0;
     p->timing = 0;
+    p->multiscale = 0;
+    p->jump_scale = 0.0;
+    p->trunc_theta = 20.0;
+    p->n_clusters = 0;
+    p->kmeans_iters = kKmeansIters;
 }
 
 int skh_create(skh_ctx **out, int device, void *hip_stream) {
@@ -299,7 +316,7 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
         lohi = c.take<float>(192);
         mass = c.take<double>(2);
         bad = c.take<int>(4);
-        if (split) cy.carve(c, (int)m, kp);
+        if (split) cy.carve(c, (int)m, kp, 0);
         if (!pass) {
             int rc = ensure_ws(ctx, 0, c.off);
             if (rc) return rc;
@@ -314,7 +331,7 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     const float *cols_u_lw = lwy, *cols_hn = hny, *h_cols = h;
     int m_cols = (int)m;
     if (split) {
-        int rc = cluster_start(ctx, cy, Yp, w, kp, s);
+        int rc = cluster_start(ctx, cy, Yp, w, kp, kKmeansIters, s);
         if (rc) return rc;
         SKH_HIP(hipMemcpyAsync(ctx->host, cy.poff + cy.k, sizeof(int), hipMemcpyDeviceToHost, s));
         SKH_HIP(hipStreamSynchronize(s));
@@ -383,16 +400,20 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (!(P.blur > 0.0) || !std::isfinite(P.blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
     if (!(P.scaling > 0.0 && P.scaling < 1.0))
         return fail(ctx, SKH_EINVAL, "scaling must be in (0, 1)");
-    if (std::isnan(P.reach) || std::isnan(P.diameter) || std::isnan(P.tol))
+    if (std::isnan(P.reach) || std::isnan(P.diameter) || std::isnan(P.tol) ||
+        std::isnan(P.jump_scale) || std::isnan(P.trunc_theta))
         return fail(ctx, SKH_EINVAL, "NaN parameter");
-    if (P.extra_iters < 0 || P.max_iters < 0) return fail(ctx, SKH_EINVAL, "negative iteration count");
+    if (P.extra_iters < 0 || P.max_iters < 0 || P.kmeans_iters < 0 || P.n_clusters < 0)
+        return fail(ctx, SKH_EINVAL, "negative count parameter");
     if (P.precision != SKH_FP32 && P.precision != SKH_BF16_SPLIT)
         return fail(ctx, SKH_EINVAL, "unknown precision");
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 5; ++k)
         if (P.reserved[k]) return fail(ctx, SKH_EINVAL, "reserved params must be zero");
     if (P.init && (!f || !g || !p || !q))
         return fail(ctx, SKH_EINVAL, "init requires f, g, p and q");
     const bool split = P.precision == SKH_BF16_SPLIT;
+    const bool ms = P.multiscale != 0;
+    const bool clustered = split || ms;
     const int kp = split ? skh::packed_width_bf16(d) : skh::packed_width(d);
     if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 61");
     const int check_every = P.check_every < 1 ? 1 : P.check_every;
@@ -403,8 +424,9 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     hipStream_t s = ctx->stream;
     const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
 
-    // ---- Phase A: bounding box, validation, packing, clustering (split path) ----
+    // ---- Phase A: bounding box, validation, packing, clustering ----
     float *Xp, *Yp, *hnx, *hny, *lwx, *lwy, *plo, *phi, *lohi;
+    float *dist[4] = {nullptr, nullptr, nullptr, nullptr};  // xx, yy, yx, xy
     double *pmass, *mass;
     int *pbad, *bad;
     Clustered cx, cy;
@@ -423,9 +445,15 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         lohi = c.take<float>(192);
         mass = c.take<double>(2);
         bad = c.take<int>(4);
-        if (split) {
-            cx.carve(c, (int)n, kp);
-            cy.carve(c, (int)m, kp);
+        if (clustered) {
+            cx.carve(c, (int)n, kp, P.n_clusters);
+            cy.carve(c, (int)m, kp, P.n_clusters);
+        }
+        if (ms) {
+            dist[0] = c.take<float>((size_t)cx.k * cx.k);
+            dist[1] = c.take<float>((size_t)cy.k * cy.k);
+            dist[2] = c.take<float>((size_t)cy.k * cx.k);
+            dist[3] = c.take<float>((size_t)cx.k * cy.k);
         }
         if (!pass) {
             int rc = ensure_ws(ctx, 0, c.off);
@@ -467,25 +495,35 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     SKH_HIP(skh::launch_pack(x, a, n, d, kp, lohi + 128, Xp, hnx, lwx, s));
     SKH_HIP(skh::launch_pack(y, b, m, d, kp, lohi + 128, Yp, hny, lwy, s));
-    // point sets the loop runs on: the caller's order (FP32 path) or the
-    // cluster-sorted padded order (split path)
+    // point sets of the fine loop: caller order (dense FP32) or cluster order
     int64_t nn = n, mm = m;
     const float *rowx = Xp, *rowy = Yp, *hnX = hnx, *hnY = hny, *lwX = lwx, *lwY = lwy, *wX = a,
                 *wY = b;
-    if (split) {
-        int rc = cluster_start(ctx, cx, Xp, a, kp, s);
+    int t_jump = 0;
+    if (clustered) {
+        const int kmi = P.kmeans_iters;
+        int rc = cluster_start(ctx, cx, Xp, a, kp, kmi, s);
         if (rc) return rc;
-        rc = cluster_start(ctx, cy, Yp, b, kp, s);
+        rc = cluster_start(ctx, cy, Yp, b, kp, kmi, s);
         if (rc) return rc;
-        SKH_HIP(hipMemcpyAsync(hb + 1024, cx.poff + cx.k, sizeof(int), hipMemcpyDeviceToHost, s));
-        SKH_HIP(hipMemcpyAsync(hb + 1028, cy.poff + cy.k, sizeof(int), hipMemcpyDeviceToHost, s));
+        Clustered *cl2[2] = {&cx, &cy};
+        for (Clustered *cl : cl2) {
+            cl->h_poff.resize(cl->k + 1);
+            cl->h_mass.resize(cl->k);
+            cl->h_rad.resize(cl->k);
+            SKH_HIP(hipMemcpyAsync(cl->h_poff.data(), cl->poff, (cl->k + 1) * sizeof(int),
+                                   hipMemcpyDeviceToHost, s));
+            SKH_HIP(hipMemcpyAsync(cl->h_mass.data(), cl->cmass, cl->k * sizeof(float),
+                                   hipMemcpyDeviceToHost, s));
+            SKH_HIP(hipMemcpyAsync(cl->h_rad.data(), cl->radius, cl->k * sizeof(float),
+                                   hipMemcpyDeviceToHost, s));
+        }
         SKH_HIP(hipStreamSynchronize(s));
-        cx.n_pad = *reinterpret_cast<int *>(hb + 1024);
-        cy.n_pad = *reinterpret_cast<int *>(hb + 1028);
-        rc = cluster_finish(ctx, cx, Xp, a, kp, s);
-        if (rc) return rc;
-        rc = cluster_finish(ctx, cy, Yp, b, kp, s);
-        if (rc) return rc;
+        for (Clustered *cl : cl2) {
+            cl->n_pad = cl->h_poff[cl->k];
+            rc = cluster_finish(ctx, *cl, cl == &cx ? Xp : Yp, cl == &cx ? a : b, kp, s);
+            if (rc) return rc;
+        }
         nn = cx.n_pad;
         mm = cy.n_pad;
         rowx = cx.Xf;
@@ -496,6 +534,35 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         lwY = cy.lw;
         wX = cx.wp;
         wY = cy.wp;
+        if (ms) {
+            for (Clustered *cl : cl2) {
+                SKH_HIP(skh::launch_coarse_prep(cl->C, cl->cmass, cl->k, kp, cl->hnC, cl->lwC, s));
+                SKH_HIP(skh::build_row_tiles(cl->poff, cl->k, cl->tcnt, cl->toff, cl->ssum,
+                                             cl->tiles, s));
+                int nt = 0;
+                for (int c = 0; c < cl->k; ++c)
+                    nt += (cl->h_poff[c + 1] - cl->h_poff[c] + kRowTile - 1) / kRowTile;
+                cl->n_tiles = nt;
+            }
+            SKH_HIP(skh::launch_centroid_dist(cx.C, cx.k, cx.C, cx.k, kp, dist[0], s));
+            SKH_HIP(skh::launch_centroid_dist(cy.C, cy.k, cy.C, cy.k, kp, dist[1], s));
+            SKH_HIP(skh::launch_centroid_dist(cy.C, cy.k, cx.C, cx.k, kp, dist[2], s));
+            SKH_HIP(skh::launch_centroid_dist(cx.C, cx.k, cy.C, cy.k, kp, dist[3], s));
+            // coarse phase while sigma is above the jump scale (never for a warm start)
+            if (!P.init && P.jump_scale >= 0.0) {
+                double thr = P.jump_scale;
+                if (!(thr > 0.0)) {  // mass-weighted RMS cluster radius of both clouds
+                    double num = 0.0, den = 0.0;
+                    for (Clustered *cl : cl2)
+                        for (int c = 0; c < cl->k; ++c) {
+                            num += (double)cl->h_mass[c] * cl->h_rad[c] * cl->h_rad[c];
+                            den += cl->h_mass[c];
+                        }
+                    thr = den > 0.0 ? std::sqrt(num / den) : 0.0;
+                }
+                while (t_jump < L - 1 && sig[t_jump] > thr) ++t_jump;
+            }
+        }
     }
 
     // ---- Phase B: loop buffers ----
@@ -505,27 +572,78 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     // job 0: a~^{aa} (rows x, cols x); job 1: b~^{bb} (rows y, cols y);
     // job 2: a~^{a->b} (rows y, cols x); job 3: b~^{b->a} (rows x, cols y).
     const int64_t nr[4] = {nn, mm, mm, nn}, nc[4] = {nn, mm, nn, mm};
+    Clustered *rowc[4] = {&cx, &cy, &cy, &cx}, *colc[4] = {&cx, &cy, &cx, &cy};
     for (int k = 0; k < 4; ++k) {
         batch.job[k].n_rows = (int)nr[k];
         batch.job[k].n_cols = (int)nc[k];
+        if (ms) {
+            batch.job[k].n_tiles = rowc[k]->n_tiles;
+            batch.job[k].range_cap = colc[k]->k / 2 + 2;
+            batch.job[k].tiles = rowc[k]->tiles;  // marks block-sparse mode for planning
+        }
     }
     const int wgs = skh::plan_softmin_batch(batch, target_wgs(ctx));
     const int fbx = skh::finish_blocks(nn), fby = skh::finish_blocks(mm);
+    // coarse loop and jump batches (multiscale)
+    skh::SoftminBatch cbatch{}, jbatch{};
+    int cwgs = 0, jwgs = 0;
+    const int kx = cx.k, ky = cy.k;
+    if (ms && t_jump > 0) {
+        cbatch.n_jobs = 4;
+        cbatch.d = d;
+        jbatch.n_jobs = 4;
+        jbatch.d = d;
+        const int64_t cr[4] = {kx, ky, ky, kx}, cc[4] = {kx, ky, kx, ky};
+        for (int k = 0; k < 4; ++k) {
+            cbatch.job[k].n_rows = (int)cr[k];
+            cbatch.job[k].n_cols = (int)cc[k];
+            jbatch.job[k].n_rows = (int)nr[k];
+            jbatch.job[k].n_cols = (int)cc[k];
+        }
+        cwgs = skh::plan_softmin_batch(cbatch, target_wgs(ctx));
+        jwgs = skh::plan_softmin_batch(jbatch, target_wgs(ctx));
+    }
     float *u[4];
     float2 *part[4];
     double *acc, *sums;
     float *pot[4] = {f, g, p, q};
     const int64_t plen[4] = {nn, mm, nn, mm};
+    int2 *ranges[4] = {nullptr, nullptr, nullptr, nullptr};
+    int *rcount[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *cmax[4] = {nullptr, nullptr, nullptr, nullptr};  // f, g, p, q maxima per cluster
+    unsigned long long *pairs_ctr = nullptr;
+    float *uc[4], *cpot[4], *ju[4];
+    float2 *cpart[4], *jpart[4];
+    double *cacc = nullptr;
     for (int pass = 0; pass < 2; ++pass) {
         Carver c(pass ? ctx->ws[1] : nullptr);
         for (int k = 0; k < 4; ++k) u[k] = c.take<float>(nc[k]);
         for (int k = 0; k < 4; ++k) part[k] = c.take<float2>((size_t)batch.job[k].n_chunks * nr[k]);
         acc = c.take<double>((size_t)(fbx + fby) * 4);
         sums = c.take<double>(8);
-        // potentials live in the workspace unless the caller's buffers can be used in place
         for (int k = 0; k < 4; ++k) {
             float *t = c.take<float>(plen[k]);
-            if (pass && (split || !pot[k])) pot[k] = t;
+            if (pass && (clustered || !pot[k])) pot[k] = t;
+        }
+        if (ms) {
+            const int kk[4] = {kx, ky, kx, ky};
+            for (int k = 0; k < 4; ++k) {
+                ranges[k] = c.take<int2>((size_t)rowc[k]->k * batch.job[k].range_cap);
+                rcount[k] = c.take<int>(rowc[k]->k);
+                cmax[k] = c.take<float>(kk[k]);
+            }
+            pairs_ctr = c.take<unsigned long long>(1);
+            if (t_jump > 0) {
+                const int64_t cr[4] = {kx, ky, ky, kx}, cc[4] = {kx, ky, kx, ky};
+                for (int k = 0; k < 4; ++k) {
+                    uc[k] = c.take<float>(cc[k]);
+                    cpot[k] = c.take<float>(kk[k]);
+                    cpart[k] = c.take<float2>((size_t)cbatch.job[k].n_chunks * cr[k]);
+                    ju[k] = c.take<float>(cc[k]);
+                    jpart[k] = c.take<float2>((size_t)jbatch.job[k].n_chunks * nr[k]);
+                }
+                cacc = c.take<double>((size_t)(skh::finish_blocks(kx) + skh::finish_blocks(ky)) * 4);
+            }
         }
         if (!pass) {
             int rc = ensure_ws(ctx, 1, c.off);
@@ -534,7 +652,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     }
     float *F = pot[0], *G = pot[1], *Pp = pot[2], *Q = pot[3];
     if (P.init) {
-        if (split) {
+        if (clustered) {
             SKH_HIP(skh::launch_permute(f, cx.perm_pad, cx.n_pad, F, s));
             SKH_HIP(skh::launch_permute(p, cx.perm_pad, cx.n_pad, Pp, s));
             SKH_HIP(skh::launch_permute(g, cy.perm_pad, cy.n_pad, G, s));
@@ -546,15 +664,93 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         SKH_HIP(hipMemsetAsync(G, 0, mm * sizeof(float), s));
         SKH_HIP(hipMemsetAsync(Q, 0, mm * sizeof(float), s));
     }
-    {
+    if (ms) SKH_HIP(hipMemsetAsync(pairs_ctr, 0, sizeof(unsigned long long), s));
+
+    // ---- Coarse phase: the loop on the K-means centres, then the jump ----
+    double pairs = 0.0, dense_pairs = 0.0;
+    const double pairs_per_iter = (double)n * n + (double)m * m + 2.0 * (double)n * m;
+    if (ms && t_jump > 0) {
+        float *Fc = cpot[0], *Gc = cpot[1], *Pc = cpot[2], *Qc = cpot[3];
+        for (int k = 0; k < 4; ++k) SKH_HIP(hipMemsetAsync(cpot[k], 0, (k % 2 ? ky : kx) * sizeof(float), s));
         const double e0 = sigma_at(0) * sigma_at(0);
+        SKH_HIP(skh::launch_col_offsets(cx.lwC, Pc, cx.hnC, kx, e0, uc[0], s));
+        SKH_HIP(skh::launch_col_offsets(cy.lwC, Qc, cy.hnC, ky, e0, uc[1], s));
+        SKH_HIP(skh::launch_col_offsets(cx.lwC, Fc, cx.hnC, kx, e0, uc[2], s));
+        SKH_HIP(skh::launch_col_offsets(cy.lwC, Gc, cy.hnC, ky, e0, uc[3], s));
+        const float *crow[4] = {cx.C, cy.C, cy.C, cx.C}, *ccol[4] = {cx.C, cy.C, cx.C, cy.C};
+        for (int k = 0; k < 4; ++k) {
+            cbatch.job[k].rows = crow[k];
+            cbatch.job[k].cols = ccol[k];
+            cbatch.job[k].u = uc[k];
+            cbatch.job[k].part = cpart[k];
+        }
+        skh::FinishSide csx{}, csy{};
+        csx.part_self = cpart[0];
+        csx.part_cross = cpart[3];
+        csx.chunks_self = cbatch.job[0].n_chunks;
+        csx.chunks_cross = cbatch.job[3].n_chunks;
+        csx.n = kx;
+        csx.hn = cx.hnC;
+        csx.lw = cx.lwC;
+        csx.w = cx.cmass;
+        csx.pot_self = Pc;
+        csx.pot_cross = Fc;
+        csx.u_self = uc[0];
+        csx.u_cross = uc[2];
+        csy.part_self = cpart[1];
+        csy.part_cross = cpart[2];
+        csy.chunks_self = cbatch.job[1].n_chunks;
+        csy.chunks_cross = cbatch.job[2].n_chunks;
+        csy.n = ky;
+        csy.hn = cy.hnC;
+        csy.lw = cy.lwC;
+        csy.w = cy.cmass;
+        csy.pot_self = Qc;
+        csy.pot_cross = Gc;
+        csy.u_self = uc[1];
+        csy.u_cross = uc[3];
+        const double cpairs = (double)kx * kx + (double)ky * ky + 2.0 * (double)kx * ky;
+        for (int it = 0; it < t_jump; ++it) {
+            const double sigma = sigma_at(it), eps = sigma * sigma, sn = sigma_at(it + 1);
+            cbatch.kscale = (float)(kLog2e / eps);
+            SKH_HIP(skh::launch_softmin(cbatch, kp, SKH_FP32, cwgs, s));
+            SKH_HIP(skh::launch_iteration_finish(csx, csy, eps, damping(sigma, P.reach), rho,
+                                                 balanced ? 1 : 0, sn * sn, 0, cacc, s));
+            pairs += cpairs;
+        }
+        // jump: one softmin of the fine points against the other cloud's coarse
+        // measure, at the scale of the last coarse iteration
+        const double sj = sigma_at(t_jump - 1), ej = sj * sj, lj = damping(sj, P.reach);
+        SKH_HIP(skh::launch_col_offsets(cx.lwC, Pc, cx.hnC, kx, ej, ju[0], s));
+        SKH_HIP(skh::launch_col_offsets(cy.lwC, Qc, cy.hnC, ky, ej, ju[1], s));
+        SKH_HIP(skh::launch_col_offsets(cx.lwC, Fc, cx.hnC, kx, ej, ju[2], s));
+        SKH_HIP(skh::launch_col_offsets(cy.lwC, Gc, cy.hnC, ky, ej, ju[3], s));
+        const float *jrow[4] = {rowx, rowy, rowy, rowx};
+        for (int k = 0; k < 4; ++k) {
+            jbatch.job[k].rows = jrow[k];
+            jbatch.job[k].cols = ccol[k];
+            jbatch.job[k].u = ju[k];
+            jbatch.job[k].part = jpart[k];
+        }
+        jbatch.kscale = (float)(kLog2e / ej);
+        SKH_HIP(skh::launch_softmin(jbatch, kp, SKH_FP32, jwgs, s));
+        const float *jhn[4] = {hnX, hnY, hnY, hnX};
+        float *jout[4] = {Pp, Q, G, F};
+        for (int k = 0; k < 4; ++k)
+            SKH_HIP(skh::launch_softmin_finish(jpart[k], jbatch.job[k].n_chunks, nr[k], jhn[k], ej,
+                                               lj, jout[k], s));
+        pairs += (double)n * kx + (double)m * ky + (double)m * kx + (double)n * ky;
+    }
+
+    // ---- Fine phase ----
+    {
+        const double e0 = sigma_at(t_jump) * sigma_at(t_jump);
         SKH_HIP(skh::launch_col_offsets(lwX, Pp, hnX, nn, e0, u[0], s));
         SKH_HIP(skh::launch_col_offsets(lwY, Q, hnY, mm, e0, u[1], s));
         SKH_HIP(skh::launch_col_offsets(lwX, F, hnX, nn, e0, u[2], s));
         SKH_HIP(skh::launch_col_offsets(lwY, G, hnY, mm, e0, u[3], s));
     }
     const float *rowp[4] = {rowx, rowy, rowy, rowx}, *colp[4] = {Xp, Yp, Xp, Yp};
-    const Clustered *colc[4] = {&cx, &cy, &cx, &cy};
     for (int k = 0; k < 4; ++k) {
         skh::SoftminJob &J = batch.job[k];
         J.rows = rowp[k];
@@ -566,7 +762,12 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
             J.col_blk_cluster = colc[k]->blk;
             J.col_centroids = colc[k]->C;
         } else {
-            J.cols = colp[k];
+            J.cols = clustered ? colc[k]->Xf : colp[k];
+        }
+        if (ms) {
+            J.tiles = rowc[k]->tiles;
+            J.ranges = ranges[k];
+            J.range_count = rcount[k];
         }
     }
     skh::FinishSide sx{}, sy{};
@@ -599,24 +800,50 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         int rc = ensure_events(ctx, 2 * (size_t)cap);
         if (rc) return rc;
     }
-    double err = -1.0, eps = P.blur * P.blur, pairs = 0.0;
-    int it = 0, checks = 0;
+    double err = -1.0, eps = P.blur * P.blur;
+    int it = t_jump, checks = 0, launches = 0;
     bool converged = false;
-    // pairs of real points (padding excluded)
-    const double pairs_per_iter = (double)n * n + (double)m * m + 2.0 * (double)n * m;
     for (; it < cap; ++it) {
         const double sigma = sigma_at(it);
         eps = sigma * sigma;
         const double lam = damping(sigma, P.reach);
         const double sn = sigma_at(it + 1);
+        if (ms) {  // cluster-block truncation from the current dual vectors
+            SKH_HIP(skh::launch_cluster_max(F, wX, cx.poff, kx, cmax[0], s));
+            SKH_HIP(skh::launch_cluster_max(G, wY, cy.poff, ky, cmax[1], s));
+            SKH_HIP(skh::launch_cluster_max(Pp, wX, cx.poff, kx, cmax[2], s));
+            SKH_HIP(skh::launch_cluster_max(Q, wY, cy.poff, ky, cmax[3], s));
+            const int keep_all = P.trunc_theta > 0.0 ? 0 : 1;
+            const double te = P.trunc_theta * eps;
+            // rows x / cols x (p), rows y / cols y (q), rows y / cols x (g, f), rows x / cols y (f, g)
+            SKH_HIP(skh::launch_block_ranges(kx, kx, cmax[2], cmax[2], dist[0], cx.radius, cx.radius,
+                                             cx.poff, cx.off, cx.off, lam, te, keep_all,
+                                             batch.job[0].range_cap, ranges[0], rcount[0],
+                                             pairs_ctr, s));
+            SKH_HIP(skh::launch_block_ranges(ky, ky, cmax[3], cmax[3], dist[1], cy.radius, cy.radius,
+                                             cy.poff, cy.off, cy.off, lam, te, keep_all,
+                                             batch.job[1].range_cap, ranges[1], rcount[1],
+                                             pairs_ctr, s));
+            SKH_HIP(skh::launch_block_ranges(ky, kx, cmax[1], cmax[0], dist[2], cy.radius, cx.radius,
+                                             cx.poff, cx.off, cy.off, lam, te, keep_all,
+                                             batch.job[2].range_cap, ranges[2], rcount[2],
+                                             pairs_ctr, s));
+            SKH_HIP(skh::launch_block_ranges(kx, ky, cmax[0], cmax[1], dist[3], cx.radius, cy.radius,
+                                             cy.poff, cy.off, cx.off, lam, te, keep_all,
+                                             batch.job[3].range_cap, ranges[3], rcount[3],
+                                             pairs_ctr, s));
+        } else {
+            pairs += pairs_per_iter;
+        }
+        dense_pairs += pairs_per_iter;
         batch.kscale = (float)(kLog2e / eps);
-        if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * it], s));
+        if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * launches], s));
         if (split)
             SKH_HIP(skh::launch_softmin_bf16(batch, kp, wgs, s));
         else
             SKH_HIP(skh::launch_softmin(batch, kp, P.precision, wgs, s));
-        if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * it + 1], s));
-        pairs += pairs_per_iter;
+        if (P.timing) SKH_HIP(hipEventRecord(ctx->events[2 * launches + 1], s));
+        ++launches;
         bool check = (it == cap - 1);
         if (P.tol > 0.0 && it >= total && ((it - total + 1) % check_every == 0)) check = true;
         SKH_HIP(skh::launch_iteration_finish(sx, sy, eps, lam, rho, balanced ? 1 : 0, sn * sn,
@@ -650,28 +877,33 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
                                          &nbd, s));
     SKH_HIP(skh::launch_sum_partials(acc, nbd, 4, sums, s));
     SKH_HIP(hipMemcpyAsync(hb + 1024, sums, sizeof(double), hipMemcpyDeviceToHost, s));
-    if (split) {
+    if (ms) SKH_HIP(hipMemcpyAsync(hb + 1088, pairs_ctr, sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, s));
+    if (clustered) {
         float *outs[4] = {f, g, p, q};
         const Clustered *cl[4] = {&cx, &cy, &cx, &cy};
         for (int k = 0; k < 4; ++k)
-            if (outs[k]) SKH_HIP(skh::launch_unpermute(pot[k], cl[k]->perm_pad, cl[k]->n_pad, outs[k], s));
+            if (outs[k])
+                SKH_HIP(skh::launch_unpermute(pot[k], cl[k]->perm_pad, cl[k]->n_pad, outs[k], s));
     }
     SKH_HIP(hipStreamSynchronize(s));
     double S = *reinterpret_cast<const double *>(hb + 1024);
+    if (ms) pairs += (double)*reinterpret_cast<const unsigned long long *>(hb + 1088);
     const double eps_blur = P.blur * P.blur;
     if (!balanced) S = -(rho + 0.5 * eps_blur) * S;
     if (S_out) *S_out = S;
     double ms_softmin = 0.0;
     if (P.timing) {
-        for (int k = 0; k < it; ++k) {
-            float ms = 0.0f;
-            SKH_HIP(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
-            ms_softmin += ms;
+        for (int k = 0; k < launches; ++k) {
+            float t_ms = 0.0f;
+            SKH_HIP(hipEventElapsedTime(&t_ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+            ms_softmin += t_ms;
         }
     }
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->softmin_launches = it;
+        stats->softmin_launches = launches;
+        stats->coarse_iters = t_jump;
         stats->ms_softmin = ms_softmin;
         stats->iters = it;
         stats->n_scales = L;
@@ -681,6 +913,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         stats->eps = eps;
         stats->marginal_err = err;
         stats->pairs = pairs;
+        stats->dense_pairs = dense_pairs;
         stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                                     t_start)
                               .count();

@@ -38,6 +38,16 @@ struct SoftminJob {
     int n_chunks;       // column chunks
     int chunk_cols;     // columns per chunk (multiple of kColsPerTile)
     int wg_begin;       // first workgroup of this job in the launch
+    // Block-sparse mode (tiles != NULL): workgroup w handles tiles[w] =
+    // {row_begin, row_end, row_cluster, 0} (rows of one cluster, at most
+    // kRowsPerBlock) against the column ranges ranges[cluster * range_cap ..
+    // + range_count[cluster]), each [begin, end) in padded column order; one
+    // chunk (n_chunks = 1).
+    const int4 *tiles;
+    const int2 *ranges;
+    const int *range_count;
+    int range_cap;
+    int n_tiles;
 };
 
 struct SoftminBatch {
@@ -108,6 +118,22 @@ hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, flo
                             hipStream_t s);
 hipError_t launch_permute(const float *src, const int *perm_pad, int n_pad, float *out,
                           hipStream_t s);
+
+// ---- Coarse-to-fine support (multiscale.hip) ----
+hipError_t launch_cluster_max(const float *pot, const float *w, const int *poff, int k, float *out,
+                              hipStream_t s);
+hipError_t launch_centroid_dist(const float *CI, int ki, const float *CJ, int kj, int kp,
+                                float *dist, hipStream_t s);
+hipError_t launch_block_ranges(int ki, int kj, const float *rmax, const float *cmax,
+                               const float *dist, const float *rrad, const float *crad,
+                               const int *cpoff, const int *coff, const int *roff, double lam,
+                               double theta_eps, int keep_all, int cap, int2 *ranges, int *count,
+                               unsigned long long *pairs, hipStream_t s);
+hipError_t launch_coarse_prep(const float *C, const float *cmass, int k, int kp, float *hn,
+                              float *lw, hipStream_t s);
+// tiles: ceil(size_c / kRowsPerBlock) entries per cluster (cnt, toff: k + 1 ints)
+hipError_t build_row_tiles(const int *poff, int k, int *cnt, int *toff, int *scan_sums,
+                           int4 *tiles, hipStream_t s);
 
 // Bounding box and validation of one cloud.
 //   plo/phi: nb x 64 partial min/max, pmass: nb FP64 partial weight sums,

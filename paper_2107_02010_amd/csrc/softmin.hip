@@ -51,21 +51,43 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
         if (t < B.n_jobs && wg >= B.job[t].wg_begin) q = t;
-    const float *__restrict__ rows = B.job[q].rows;  // FP32 packed
-    const float *__restrict__ cols = B.job[q].cols;
-    const float *__restrict__ u = B.job[q].u;
-    float2 *__restrict__ part = B.job[q].part;
-    const int n_rows = B.job[q].n_rows, n_cols = B.job[q].n_cols;
-    const int row_tiles = B.job[q].row_tiles, chunk_cols = B.job[q].chunk_cols;
-    const int local = wg - B.job[q].wg_begin;
-    const int rt = local % row_tiles, chunk = local / row_tiles;
+    const SoftminJob &J = B.job[q];
+    const float *__restrict__ rows = J.rows;  // FP32 packed
+    const float *__restrict__ cols = J.cols;
+    const float *__restrict__ u = J.u;
+    float2 *__restrict__ part = J.part;
+    const int n_rows = J.n_rows, n_cols = J.n_cols;
+    const int local = wg - J.wg_begin;
     const int d = B.d;
     const float kscale = B.kscale;
 
+    // rows [rb, re) and the column ranges of this workgroup
+    int rb, re, chunk, nranges, cl_row = 0;
+    const int2 *rng = nullptr;
+    int c_begin = 0, c_end = 0;
+    if (J.tiles) {
+        const int4 t = J.tiles[local];
+        rb = t.x;
+        re = t.y;
+        cl_row = t.z;
+        chunk = 0;
+        rng = J.ranges + (size_t)cl_row * J.range_cap;
+        nranges = J.range_count[cl_row];
+    } else {
+        const int rt = local % J.row_tiles;
+        chunk = local / J.row_tiles;
+        rb = rt * kRowsPerBlock;
+        re = min(n_rows, rb + kRowsPerBlock);
+        c_begin = chunk * J.chunk_cols;
+        c_end = min(n_cols, c_begin + J.chunk_cols);
+        nranges = 1;
+    }
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, li = lane & 31;
-    const int i = rt * kRowsPerBlock + wave * 32 + li;
-    const int ic = i < n_rows ? i : n_rows - 1;
+    const int i = rb + wave * 32 + li;
+    const int ic = i < re ? i : re - 1;
+    const bool wave_active = rb + wave * 32 < re;
 
     // Row operand: x_i scaled by k, slot d = 1.
     float xr[H];
@@ -88,10 +110,14 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         for (int s = 0; s < H; ++s) xr[s] = (h * H + s == d) ? 1.0f : xr[s] * kscale;
     }
 
-    const int c_begin = chunk * chunk_cols;
-    const int c_end = min(n_cols, c_begin + chunk_cols);
     float m = ninf(), acc_sum = 0.0f;
 
+    for (int ri = 0; ri < nranges; ++ri) {
+    if (rng) {
+        const int2 r = rng[ri];
+        c_begin = r.x;
+        c_end = r.y;
+    }
     for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
         __syncthreads();
         for (int e = tid; e < kColsPerTile * V4; e += 256) {
@@ -111,7 +137,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         }
         __syncthreads();
         const int nvalid = c_end - j0;
-        const int nblk = min(kColsPerTile / 32, (nvalid + 31) >> 5);
+        const int nblk = wave_active ? min(kColsPerTile / 32, (nvalid + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
             v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -132,6 +158,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
             }
         }
     }
+    }
 
     // Merge the two lane halves that hold the same row.
     const float m2 = __shfl_xor(m, 32, 64);
@@ -139,7 +166,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
     const float M = fmaxf(m, m2);
     float S = 0.0f;
     if (M > ninf()) S = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
-    if (h == 0 && i < n_rows) part[(size_t)chunk * n_rows + i] = make_float2(M, S);
+    if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, S);
 }
 
 int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
@@ -154,6 +181,13 @@ int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
     int total = 0;
     for (int q = 0; q < b.n_jobs; ++q) {
         SoftminJob &J = b.job[q];
+        if (J.tiles) {  // block-sparse: one workgroup per row tile, one chunk
+            J.chunk_cols = 0;
+            J.n_chunks = 1;
+            J.wg_begin = total;
+            total += J.n_tiles;
+            continue;
+        }
         int tiles = (J.n_cols + kColsPerTile - 1) / kColsPerTile;
         int tiles_per_chunk = (tiles + want_chunks - 1) / want_chunks;
         if (tiles_per_chunk < 1) tiles_per_chunk = 1;

@@ -53,16 +53,36 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
     const float *__restrict__ u = J.u;
     float2 *__restrict__ part = J.part;
     const int n_rows = J.n_rows, n_cols = J.n_cols;
-    const int row_tiles = J.row_tiles, chunk_cols = J.chunk_cols;
     const int local = wg - J.wg_begin;
-    const int rt = local % row_tiles, chunk = local / row_tiles;
     const int d = B.d;
     const float kscale = B.kscale;
 
+    // rows [rb, re) and the column ranges of this workgroup
+    int rb, re, chunk, nranges;
+    const int2 *rng = nullptr;
+    int c_begin = 0, c_end = 0;
+    if (J.tiles) {
+        const int4 t = J.tiles[local];
+        rb = t.x;
+        re = t.y;
+        chunk = 0;
+        rng = J.ranges + (size_t)t.z * J.range_cap;
+        nranges = J.range_count[t.z];
+    } else {
+        const int rt = local % J.row_tiles;
+        chunk = local / J.row_tiles;
+        rb = rt * kRowsPerBlock;
+        re = min(n_rows, rb + kRowsPerBlock);
+        c_begin = chunk * J.chunk_cols;
+        c_end = min(n_cols, c_begin + J.chunk_cols);
+        nranges = 1;
+    }
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, li = lane & 31;
-    const int i = rt * kRowsPerBlock + wave * 32 + li;
-    const int ic = i < n_rows ? i : n_rows - 1;
+    const int i = rb + wave * 32 + li;
+    const int ic = i < re ? i : re - 1;
+    const bool wave_active = rb + wave * 32 < re;
 
     // Row: k * x_i in FP32 (for the cluster shift) and its bf16 hi/lo split.
     float xf[H];
@@ -92,11 +112,15 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
         }
     }
 
-    const int c_begin = chunk * chunk_cols;
-    const int c_end = min(n_cols, c_begin + chunk_cols);
     float m = -__builtin_huge_valf(), acc_sum = 0.0f, shift = 0.0f;
     int cur_cluster = -1;
 
+    for (int ri = 0; ri < nranges; ++ri) {
+    if (rng) {
+        const int2 r = rng[ri];
+        c_begin = r.x;
+        c_end = r.y;
+    }
     for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
         __syncthreads();
         for (int e = tid; e < kColsPerTile * V16; e += 256) {
@@ -135,7 +159,7 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
             lcent[t][dd] = cl >= 0 ? cent[(size_t)cl * KP + dd] : 0.0f;
         }
         __syncthreads();
-        const int nblk = min(kColsPerTile / 32, (c_end - j0 + 31) >> 5);
+        const int nblk = wave_active ? min(kColsPerTile / 32, (c_end - j0 + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
             const int cl = lcl[jb];
             if (cl != cur_cluster) {  // wave-uniform
@@ -171,13 +195,14 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
             }
         }
     }
+    }
 
     const float m2 = __shfl_xor(m, 32, 64);
     const float s2 = __shfl_xor(acc_sum, 32, 64);
     const float M = fmaxf(m, m2);
     float Ssum = 0.0f;
     if (M > -__builtin_huge_valf()) Ssum = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
-    if (h == 0 && i < n_rows) part[(size_t)chunk * n_rows + i] = make_float2(M, Ssum);
+    if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, Ssum);
 }
 
 hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s) {

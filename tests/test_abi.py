@@ -39,7 +39,9 @@ def test_params_default_and_struct_layout():
     p = _lib.default_params()
     assert p.blur == 0.05 and math.isinf(p.reach) and p.scaling == 0.9
     assert p.tol == 0.0 and p.extra_iters == 0 and p.max_iters == 1000 and p.check_every == 5
-    assert p.precision == _lib.SKH_FP32 and p.init == 0
+    assert p.precision == _lib.SKH_FP32 and p.init == 0 and p.timing == 0
+    assert p.multiscale == 0 and p.jump_scale == 0.0 and p.trunc_theta == 20.0
+    assert p.n_clusters == 0 and p.kmeans_iters == 10
 
 
 def test_struct_layout_matches_c_compiler(tmp_path):

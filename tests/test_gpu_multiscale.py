@@ -1,0 +1,78 @@
+"""GPU checks of the coarse-to-fine path (Section 2): K-means coarse phase, jump to
+the fine points, cluster-block kernel truncation and the block-sparse softmin.
+
+* no coarse phase and every block kept: the block-sparse machinery must give the
+  dense result (oracle, same schedule), FP32 and BF16 split;
+* truncation alone (theta = 20): entries dropped are below e^-20 of their row, so
+  the result stays at the dense FP32 tolerance;
+* full multiscale in converged mode reaches the same fixed point as the dense
+  oracle (the coarse start and the truncation change the path, not the limit).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import cuda, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(x, a, y, b, **kw):
+    import paper_2107_02010_amd as skh
+    note(f"multiscale n={len(x)} m={len(y)} d={x.shape[1]} {kw}")
+    S, pot, st = skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), potentials=True, **kw)
+    return S, {k: host(v) for k, v in pot.items()}, st
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 1e-5), ("bf16x3", 1e-3)])
+@pytest.mark.parametrize("reach", [None, 20.0])
+def test_block_sparse_keep_all_equals_dense(precision, rtol, reach):
+    x, a, y, b = synth.fiber_pair(3000, 20, seed=21)
+    kw = dict(blur=1.0, reach=reach, scaling=0.8, extra_iters=2)
+    S, pot, st = _run(x, a, y, b, multiscale=True, jump_scale=-1.0, trunc_theta=0.0,
+                      precision=precision, **kw)
+    Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 1.0, reach, scaling=0.8, extra_iters=2)
+    assert st["coarse_iters"] == 0 and st["iters"] == r["iters"]
+    assert st["pairs"] == pytest.approx(st["dense_pairs"], rel=1e-12)
+    assert S == pytest.approx(Sr, rel=rtol)
+
+
+@pytest.mark.parametrize("reach", [None, 20.0])
+def test_truncation_only_stays_at_fp32_tolerance(reach):
+    x, a, y, b = synth.fiber_pair(4000, 25, seed=22)
+    kw = dict(blur=1.0, reach=reach, scaling=0.8, extra_iters=3)
+    S, pot, st = _run(x, a, y, b, multiscale=True, jump_scale=-1.0, trunc_theta=20.0, **kw)
+    Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 1.0, reach, scaling=0.8, extra_iters=3)
+    print(f"truncation: kept {st['pairs'] / st['dense_pairs']:.3f} of the pairs, "
+          f"S={S:.9g} oracle={Sr:.9g}")
+    assert st["pairs"] < st["dense_pairs"]
+    assert S == pytest.approx(Sr, rel=1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_multiscale_converges_to_dense_fixed_point(precision):
+    # The averaged loop needs thousands of iterations at this tolerance, beyond
+    # what the FP64 oracle finishes in seconds; the dense FP32 GPU path (pinned to
+    # the oracle in schedule and converged mode elsewhere) is the reference here.
+    x, a, y, b = synth.fiber_pair(4000, 25, seed=23)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.9, tol=1e-4, max_iters=20000, check_every=5)
+    S, pot, st = _run(x, a, y, b, multiscale=True, precision=precision, **kw)
+    Sd, potd, std = _run(x, a, y, b, **kw)
+    print(f"multiscale {precision}: coarse iters {st['coarse_iters']}, fine iters "
+          f"{st['iters'] - st['coarse_iters']}, kept {st['pairs'] / max(st['dense_pairs'], 1):.3f}, "
+          f"S={S:.9g} dense={Sd:.9g} (dense iters {std['iters']})")
+    assert st["converged"] == 1 and std["converged"] == 1
+    assert st["coarse_iters"] > 0
+    assert S == pytest.approx(Sd, rel=1e-5 if precision == "fp32" else 1e-3)
+    # unbalanced potentials are unique: compare them too
+    scale = max(1.0, np.abs(potd["f"]).max())
+    np.testing.assert_allclose(pot["f"], potd["f"], atol=(1e-4 if precision == "fp32" else 1e-2) * scale)
+
+
+def test_multiscale_blob_config_balanced():
+    x, a, y, b = synth.blob_pair(2000, seed=0)
+    kw = dict(blur=0.01, reach=None, scaling=0.5)
+    S, pot, st = _run(x, a, y, b, multiscale=True, jump_scale=-1.0, trunc_theta=20.0, **kw)
+    Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 0.01, None, scaling=0.5)
+    assert S == pytest.approx(Sr, rel=1e-5)
