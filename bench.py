@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the Sinkhorn divergence hot path on one MI355X.
 
-A step is one full S_eps solve (every row of the hot path: bounding box and
-scale list, packing, the averaged symmetric loop of four softmins per
-iteration, the merge/averaging kernel, and the FP64 value of eq. (6)) on a
+Default workload (--workload fibers200k): a step is one full S_eps solve (every
+row of the hot path: bounding box and scale list, K-means clustering and the
+cluster-sorted layout, packing, the averaged symmetric loop of four softmins
+per iteration, the merge/averaging kernel, and the FP64 value of eq. (6)) on a
 synthetic fibre workload: n = m = 200,000 fibres, 20 points each flattened to
 60-D and scaled by 1/sqrt(20), 50 bundles, uniform weights, blur = 1 mm,
-reach = none (balanced), scaling 0.9.  Inputs are resident in HBM before the
-timed region.
+reach = none (balanced), scaling 0.9, dense.  The timed path is the chosen
+precision (BF16 hi/lo split, --precision); one plain FP32 solve of the same
+input is timed beside it.  Inputs are resident in HBM before the timed region.
+
+--workload multiscale1m: time-to-S_eps on n = m = 1,000,000 fibres (200
+bundles), reach 20 mm, blur 1 mm, K-means coarse phase with sqrt(n) clusters,
+cluster-block truncation, converged mode (marginal error <= 1e-4 checked every
+5 iterations); plain FP32 against the BF16 split.
 
 Prints one JSON line:
   value       = softmin point pairs evaluated / wall time of the timed steps (Gpair/s)
@@ -16,7 +23,7 @@ Prints one JSON line:
   cpu_baseline= the FP64 oracle's softmin on a bounded row sample of the same
                 workload, on the host cores
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3] [--n N]
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3] [--workload ...]
 """
 from __future__ import annotations
 
@@ -34,12 +41,13 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}  # MI355X dense MFMA, FP32 and BF16
 FLOP_PER_PAIR = {"fp32": 128, "bf16x3": 384}      # 64-wide contraction; x3 for the hi/lo split
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2107_02010_amd", "csrc", "softmin.hip")
+KERNEL_SRC = {"fp32": os.path.join(ROOT, "paper_2107_02010_amd", "csrc", "softmin.hip"),
+              "bf16x3": os.path.join(ROOT, "paper_2107_02010_amd", "csrc", "softmin_bf16.hip")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "softmin_fiber200k_traffic.txt")
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(precision: str) -> str:
+    return hashlib.sha256(open(KERNEL_SRC[precision], "rb").read()).hexdigest()[:16]
 
 
 def read_traffic(precision: str):
@@ -48,9 +56,9 @@ def read_traffic(precision: str):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
-    m = re.search(r"kernel_sha256_16:\s*([0-9a-f]+)", txt)
+    m = re.search(rf"kernel_sha256_16\[{precision}\]:\s*([0-9a-f]+)", txt)
     t = re.search(rf"bytes_per_launch\[{precision}\]:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != kernel_hash():
+    if not m or not t or m.group(1) != kernel_hash(precision):
         return None
     return float(t.group(1))
 
@@ -79,12 +87,91 @@ def cpu_baseline(x, y, b, target_s: float = 8.0):
                       f"60-D, eps=1 ({pairs:.3g} pairs, {dt:.1f} s)"}
 
 
+def solve_steps(skh, X, A, Y, B, steps, warmup, label, **kw):
+    import torch
+    for k in range(warmup):
+        skh.sinkhorn_divergence(X, A, Y, B, **kw)
+        print(f"[bench] {label} warmup {k + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = dict(pairs=0.0, ms_softmin=0.0, launches=0, dense_pairs=0.0)
+    S, st = None, None
+    for k in range(steps):
+        S, _, st = skh.sinkhorn_divergence(X, A, Y, B, **kw)
+        agg["pairs"] += st["pairs"]
+        agg["dense_pairs"] += st["dense_pairs"]
+        agg["ms_softmin"] += st["ms_softmin"]
+        agg["launches"] += st["softmin_launches"]
+        print(f"[bench] {label} step {k + 1}/{steps}: S={S:.10g} iters={st['iters']} "
+              f"{st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    agg["dt"] = time.perf_counter() - t0
+    agg["S"] = S
+    agg["stats"] = st
+    return agg
+
+
+def roofline(agg, precision):
+    pairs_per_launch = agg["pairs"] / agg["launches"]
+    avg_launch_s = agg["ms_softmin"] / agg["launches"] / 1e3
+    achieved = FLOP_PER_PAIR[precision] * pairs_per_launch / avg_launch_s / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": read_traffic(precision),
+            "flop_per_pair": FLOP_PER_PAIR[precision],
+            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "kernel": "k_softmin_f32<64>" if precision == "fp32" else "k_softmin_bf16<64>"}, \
+        pairs_per_launch / avg_launch_s / 1e9
+
+
+def bench_multiscale(args, skh, synth):
+    import torch
+    n = args.n if args.n != 200_000 else 1_000_000
+    print(f"[bench] generating {n} x {n} fibre clouds (200 bundles)", file=sys.stderr, flush=True)
+    x, a, y, b = synth.fiber_pair(n, 200, seed=0)
+    dev = torch.device("cuda:0")
+    X, A, Y, B = (torch.as_tensor(v).to(dev) for v in (x, a, y, b))
+    kw = dict(blur=1.0, reach=20.0, scaling=0.9, tol=1e-4, check_every=5, max_iters=20000,
+              multiscale=True, potentials=True, timing=True)
+    res = {}
+    for prec in ("fp32", "bf16x3"):
+        agg = solve_steps(skh, X, A, Y, B, 1, args.warmup, f"multiscale {prec}", precision=prec, **kw)
+        rl, kern = roofline(agg, prec)
+        st = agg["stats"]
+        res[prec] = {"time_to_S_s": round(agg["dt"], 3), "S": agg["S"], "iters": st["iters"],
+                     "coarse_iters": st["coarse_iters"], "converged": st["converged"],
+                     "marginal_err": st["marginal_err"],
+                     "kept_fraction": round(agg["pairs"] / max(agg["dense_pairs"], 1.0), 5),
+                     "gpair_s_kept": round(agg["pairs"] / agg["dt"] / 1e9, 3),
+                     "gpair_s_dense_equivalent": round(agg["dense_pairs"] / agg["dt"] / 1e9, 3),
+                     "softmin_kernel_gpair_s": round(kern, 3), "roofline": rl}
+    chosen, plain = res["bf16x3"], res["fp32"]
+    out = {
+        "metric": "time-to-S_eps, 1M x 1M 60-D fibres (multiscale, converged to 1e-4)",
+        "value": chosen["time_to_S_s"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": round(chosen["time_to_S_s"] * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"fibre clouds n=m={n}, 60-D, 200 Bezier bundles, jitter 2 mm, "
+                               "blur 1 mm, reach 20 mm, scaling 0.9, K-means sqrt(n) clusters, "
+                               "truncation theta 20, tolerance 1e-4"},
+        "plain_fp32": plain, "chosen_bf16x3": chosen,
+        "speedup_chosen_vs_plain": round(plain["time_to_S_s"] / chosen["time_to_S_s"], 3),
+        "S_rel_diff": abs(chosen["S"] - plain["S"]) / abs(plain["S"]),
+        "roofline": chosen["roofline"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
+    ap.add_argument("--workload", default="fibers200k", choices=["fibers200k", "multiscale1m"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison solve")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,44 +188,25 @@ def main() -> int:
     import paper_2107_02010_amd as skh
     import synth
 
+    if args.workload == "multiscale1m":
+        return bench_multiscale(args, skh, synth)
     print(f"[bench] generating {args.n} x {args.n} fibre clouds", file=sys.stderr, flush=True)
     x, a, y, b = synth.fiber_pair(args.n, args.bundles, seed=0)
     dev = torch.device("cuda:0")
     X, A, Y, B = (torch.as_tensor(v).to(dev) for v in (x, a, y, b))
-    kw = dict(blur=1.0, reach=None, scaling=0.9, precision=args.precision, potentials=True,
-              timing=True)
-    for k in range(args.warmup):
-        skh.sinkhorn_divergence(X, A, Y, B, **kw)
-        print(f"[bench] warmup {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pairs = 0.0
-    ms_softmin = 0.0
-    launches = 0
-    S = None
-    for k in range(args.steps):
-        S, _, st = skh.sinkhorn_divergence(X, A, Y, B, **kw)
-        pairs += st["pairs"]
-        ms_softmin += st["ms_softmin"]
-        launches += st["softmin_launches"]
-        print(f"[bench] step {k + 1}/{args.steps}: S={S:.8g} iters={st['iters']} "
-              f"{st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = pairs / dt / 1e9
-    pairs_per_launch = pairs / launches
-    avg_launch_s = ms_softmin / launches / 1e3
-    achieved = FLOP_PER_PAIR[args.precision] * pairs_per_launch / avg_launch_s / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    traffic = read_traffic(args.precision)
+    kw = dict(blur=1.0, reach=None, scaling=0.9, potentials=True, timing=True)
+    agg = solve_steps(skh, X, A, Y, B, args.steps, args.warmup, args.precision,
+                      precision=args.precision, **kw)
+    rl, kern = roofline(agg, args.precision)
+    st = agg["stats"]
     out = {
         "metric": "Gpair/s of log-sum-exp softmin (full S_eps solve, 200k x 200k 60-D fibres)",
-        "value": round(value, 3),
+        "value": round(agg["pairs"] / agg["dt"] / 1e9, 3),
         "unit": "Gpair/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "ms_per_step": round(agg["dt"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -149,15 +217,17 @@ def main() -> int:
                                "reach none, scaling 0.9, dense (no multiscale)",
                    "precision": args.precision, "iterations": st["iters"],
                    "softmins_per_iteration": 4},
-        "S": S,
-        "softmin_kernel_gpair_s": round(pairs_per_launch / avg_launch_s / 1e9, 3),
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic,
-                     "flop_per_pair": FLOP_PER_PAIR[args.precision],
-                     "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-                     "kernel": "k_softmin_f32<64>" if args.precision == "fp32" else "k_softmin_bf16<64>"},
+        "S": agg["S"],
+        "softmin_kernel_gpair_s": round(kern, 3),
+        "roofline": rl,
     }
+    if args.precision != "fp32" and not args.no_plain:
+        plain = solve_steps(skh, X, A, Y, B, 1, 0, "plain fp32", precision="fp32", **kw)
+        prl, pk = roofline(plain, "fp32")
+        out["plain_fp32"] = {"value": round(plain["pairs"] / plain["dt"] / 1e9, 3),
+                             "ms_per_step": round(plain["dt"] * 1e3, 3), "S": plain["S"],
+                             "softmin_kernel_gpair_s": round(pk, 3), "roofline": prl}
+        out["S_rel_diff_vs_fp32"] = abs(agg["S"] - plain["S"]) / abs(plain["S"])
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a row sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, y, b)

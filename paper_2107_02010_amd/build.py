@@ -27,7 +27,7 @@ ARCH = os.environ.get("SKH_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
+    "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -149,7 +149,9 @@ struct Clustered {
     int4 *tiles = nullptr;                                    // max_tiles
     int *perm_pad = nullptr, *blk = nullptr;                  // n_pad_max, n_pad_max / 32
     float *Xf = nullptr;                                      // n_pad_max x kp
-    __hip_bfloat16 *Yhi = nullptr, *Ylo = nullptr;            // n_pad_max x kp
+    __hip_bfloat16 *Yhi[2] = {nullptr, nullptr};              // n_pad_max x kp, per problem
+    __hip_bfloat16 *Ylo = nullptr;                            // n_pad_max x kp
+    float *blkcent = nullptr;                                 // (n_pad_max / 32) x kp
     float *hn = nullptr, *lw = nullptr, *wp = nullptr;        // n_pad_max
     int *perm = nullptr, *off = nullptr;                      // inside kws, set by K-means
     std::vector<int> h_poff;                                  // host copies
@@ -175,8 +177,10 @@ struct Clustered {
         perm_pad = c.take<int>(n_pad_max);
         blk = c.take<int>(n_pad_max / 32 + 1);
         Xf = c.take<float>((size_t)n_pad_max * kp);
-        Yhi = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
+        Yhi[0] = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
+        Yhi[1] = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
         Ylo = c.take<__hip_bfloat16>((size_t)n_pad_max * kp);
+        blkcent = c.take<float>((size_t)(n_pad_max / 32 + 1) * kp);
         hn = c.take<float>(n_pad_max);
         lw = c.take<float>(n_pad_max);
         wp = c.take<float>(n_pad_max);
@@ -198,8 +202,9 @@ int cluster_finish(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, 
     if (cl.n_pad < cl.n || cl.n_pad > cl.n_pad_max)
         return fail(ctx, SKH_EHIP, "inconsistent padded cluster layout");
     SKH_HIP(skh::fill_padded_layout(cl.perm, cl.off, cl.poff, cl.k, cl.perm_pad, cl.blk, s));
-    SKH_HIP(skh::launch_pack_padded(X, w, cl.perm_pad, cl.blk, cl.C, cl.n_pad, kp, cl.Xf, cl.Yhi,
-                                    cl.Ylo, cl.hn, cl.lw, cl.wp, s));
+    SKH_HIP(skh::launch_pack_padded(X, w, cl.perm_pad, cl.blk, cl.C, cl.n_pad, kp, cl.Xf,
+                                    cl.Yhi[0], cl.Yhi[1], cl.Ylo, cl.hn, cl.lw, cl.wp, s));
+    SKH_HIP(skh::launch_blk_centroids(cl.blk, cl.C, cl.n_pad / 32, kp, cl.blkcent, s));
     return SKH_OK;
 }
 
@@ -292,7 +297,7 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
         return fail(ctx, SKH_EINVAL, "unknown precision");
     const bool split = precision == SKH_BF16_SPLIT;
     const int kp = split ? skh::packed_width_bf16(d) : skh::packed_width(d);
-    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 61");
+    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 60");
     DeviceGuard guard(ctx->device);
     hipStream_t s = ctx->stream;
     const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
@@ -373,10 +378,11 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     J.u = u;
     J.part = part;
     if (split) {
-        J.cols_hi = cy.Yhi;
+        SKH_HIP(skh::launch_u_slots(u, m_cols, kp, d, cy.Yhi[0], s));
+        J.cols_hi = cy.Yhi[0];
         J.cols_lo = cy.Ylo;
         J.col_blk_cluster = cy.blk;
-        J.col_centroids = cy.C;
+        J.col_centroids = cy.blkcent;
         SKH_HIP(skh::launch_softmin_bf16(batch, kp, wgs, s));
     } else {
         J.cols = Yp;
@@ -415,7 +421,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     const bool ms = P.multiscale != 0;
     const bool clustered = split || ms;
     const int kp = split ? skh::packed_width_bf16(d) : skh::packed_width(d);
-    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 61");
+    if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 60");
     const int check_every = P.check_every < 1 ? 1 : P.check_every;
     const bool balanced = is_balanced(P.reach);
     const double rho = balanced ? 0.0 : P.reach * P.reach;
@@ -750,6 +756,17 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         SKH_HIP(skh::launch_col_offsets(lwX, F, hnX, nn, e0, u[2], s));
         SKH_HIP(skh::launch_col_offsets(lwY, G, hnY, mm, e0, u[3], s));
     }
+    // split path: the column offsets also live in the slots of each problem's hi plane
+    auto refresh_slots = [&]() -> int {
+        if (!split) return SKH_OK;
+        for (int k = 0; k < 4; ++k)
+            SKH_HIP(skh::launch_u_slots(u[k], (int)nc[k], kp, d, colc[k]->Yhi[k / 2], s));
+        return SKH_OK;
+    };
+    {
+        int rc = refresh_slots();
+        if (rc) return rc;
+    }
     const float *rowp[4] = {rowx, rowy, rowy, rowx}, *colp[4] = {Xp, Yp, Xp, Yp};
     for (int k = 0; k < 4; ++k) {
         skh::SoftminJob &J = batch.job[k];
@@ -757,10 +774,10 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         J.u = u[k];
         J.part = part[k];
         if (split) {
-            J.cols_hi = colc[k]->Yhi;
+            J.cols_hi = colc[k]->Yhi[k / 2];  // problems 0, 1: self; 2, 3: cross
             J.cols_lo = colc[k]->Ylo;
             J.col_blk_cluster = colc[k]->blk;
-            J.col_centroids = colc[k]->C;
+            J.col_centroids = colc[k]->blkcent;
         } else {
             J.cols = clustered ? colc[k]->Xf : colp[k];
         }
@@ -848,6 +865,10 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         if (P.tol > 0.0 && it >= total && ((it - total + 1) % check_every == 0)) check = true;
         SKH_HIP(skh::launch_iteration_finish(sx, sy, eps, lam, rho, balanced ? 1 : 0, sn * sn,
                                              check ? 1 : 0, acc, s));
+        {
+            int rc = refresh_slots();
+            if (rc) return rc;
+        }
         if (check) {
             SKH_HIP(skh::launch_sum_partials(acc, fbx, 4, sums, s));
             SKH_HIP(skh::launch_sum_partials(acc + (size_t)fbx * 4, fby, 4, sums + 4, s));

@@ -277,14 +277,18 @@ __global__ __launch_bounds__(kT) void k_padded_layout(const int *__restrict__ pe
 
 // Gathers one cloud into the padded cluster order.
 //   Xf  : n_pad x KP FP32, centred coordinates (row operand and norms)
-//   Yhi/Ylo : n_pad x KP bf16, hi/lo split of x - c_{cluster} (column operand)
+//   Yhi0/Yhi1/Ylo : n_pad x KP bf16, hi/lo split of x - c_{cluster} (column
+//         operand); the two hi copies belong to the two problems that read the
+//         cloud as columns and carry 1.0 in slot KP-1 (their offset slots are
+//         filled per iteration)
 //   hn, lw, wp : half squared norms, log weights (-inf on padding), weights (0 on padding)
 template <int KP>
 __global__ __launch_bounds__(kT) void k_pack_padded(
     const float *__restrict__ X, const float *__restrict__ w, const int *__restrict__ perm_pad,
     const int *__restrict__ blk_cluster, const float *__restrict__ C, int n_pad,
-    float *__restrict__ Xf, __hip_bfloat16 *__restrict__ Yhi, __hip_bfloat16 *__restrict__ Ylo,
-    float *__restrict__ hn, float *__restrict__ lw, float *__restrict__ wp) {
+    float *__restrict__ Xf, __hip_bfloat16 *__restrict__ Yhi0, __hip_bfloat16 *__restrict__ Yhi1,
+    __hip_bfloat16 *__restrict__ Ylo, float *__restrict__ hn, float *__restrict__ lw,
+    float *__restrict__ wp) {
     const int p = blockIdx.x * kT + threadIdx.x;
     if (p >= n_pad) return;
     const int i = perm_pad[p];
@@ -295,15 +299,26 @@ __global__ __launch_bounds__(kT) void k_pack_padded(
         Xf[(size_t)p * KP + d] = v;
         s += (double)v * (double)v;
         const float dv = i >= 0 ? v - C[(size_t)c * KP + d] : 0.0f;
-        const __hip_bfloat16 hi = __float2bfloat16(dv);
+        __hip_bfloat16 hi = __float2bfloat16(dv);
         const __hip_bfloat16 lo = __float2bfloat16(dv - __bfloat162float(hi));
-        Yhi[(size_t)p * KP + d] = hi;
+        if (d == KP - 1) hi = __float2bfloat16(1.0f);
+        Yhi0[(size_t)p * KP + d] = hi;
+        Yhi1[(size_t)p * KP + d] = hi;
         Ylo[(size_t)p * KP + d] = lo;
     }
     hn[p] = (float)(0.5 * s);
     const float wi = i >= 0 ? (w ? w[i] : 1.0f) : 0.0f;
     wp[p] = wi;
     lw[p] = wi > 0.0f ? (float)log((double)wi) : -__builtin_huge_valf();
+}
+
+__global__ __launch_bounds__(kT) void k_blk_centroids(const int *__restrict__ blk_cluster,
+                                                      const float *__restrict__ C, int nblk, int kp,
+                                                      float *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= (int64_t)nblk * kp) return;
+    const int b = (int)(e / kp), t = (int)(e % kp);
+    out[e] = C[(size_t)blk_cluster[b] * kp + t];
 }
 
 // out[perm_pad[p]] = in[p] for real points; in[p] = src[perm_pad[p]] (0 on padding).
@@ -413,10 +428,18 @@ hipError_t fill_padded_layout(const int *perm, const int *off, const int *poff, 
 
 hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pad,
                               const int *blk_cluster, const float *C, int n_pad, int kp, float *Xf,
-                              __hip_bfloat16 *Yhi, __hip_bfloat16 *Ylo, float *hn, float *lw,
-                              float *wp, hipStream_t s) {
+                              __hip_bfloat16 *Yhi0, __hip_bfloat16 *Yhi1, __hip_bfloat16 *Ylo,
+                              float *hn, float *lw, float *wp, hipStream_t s) {
     SKH_KP_DISPATCH(kp, k_pack_padded, dim3(blocks(n_pad)), dim3(kT), 0, s, X, w, perm_pad,
-                    blk_cluster, C, n_pad, Xf, Yhi, Ylo, hn, lw, wp);
+                    blk_cluster, C, n_pad, Xf, Yhi0, Yhi1, Ylo, hn, lw, wp);
+    return hipGetLastError();
+}
+
+hipError_t launch_blk_centroids(const int *blk_cluster, const float *C, int nblk, int kp,
+                                float *blk_cent, hipStream_t s) {
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blk_centroids, dim3(blocks((int64_t)nblk * kp)), dim3(kT), 0, s,
+                       blk_cluster, C, nblk, kp, blk_cent);
     return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ namespace skh {
 // reserved for the augmented term of the softmin contraction, the rest is 0.
 int packed_width(int d);
 // Width of the packed rows for the BF16 split path: slots d, d+1, d+2 carry the
-// three bf16 terms of the column offset, and KP is 16, 32 or 64 (0: d too large).
+// three bf16 terms of the column offset and slot KP-1 the row reference, so
+// d + 4 <= KP; KP is 16, 32 or 64 (0: d too large).
 int packed_width_bf16(int d);
 
 constexpr int kRowsPerBlock = 128;  // 4 waves x 32 rows
@@ -27,10 +28,11 @@ constexpr int kMaxJobs = 4;
 struct SoftminJob {
     const float *rows;  // n_rows x KP packed FP32 (centred coordinates)
     const float *cols;  // FP32 path: n_cols x KP packed
-    const __hip_bfloat16 *cols_hi;  // split path: n_cols x KP, hi part of y_j - c_J
-    const __hip_bfloat16 *cols_lo;  // split path: lo part
+    const __hip_bfloat16 *cols_hi;  // split path: n_cols x KP, hi part of y_j - c_J, with this
+                                    // problem's column offsets in slots d..d+2 and 1.0 in KP-1
+    const __hip_bfloat16 *cols_lo;  // split path: lo part (slots d.. are zero)
     const int *col_blk_cluster;     // split path: cluster of each 32-column block
-    const float *col_centroids;     // split path: cluster centres, KP floats each
+    const float *col_centroids;     // split path: centre of each 32-column block's cluster (KP)
     const float *u;     // n_cols log2-domain column offsets; -inf = no mass
     float2 *part;       // n_chunks x n_rows
     int n_rows, n_cols;
@@ -65,6 +67,9 @@ int plan_softmin_batch(SoftminBatch &b, int target_wgs);
 hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
                           hipStream_t s);
 hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s);
+// u -> three bf16 terms in slots d..d+2 of a packed hi plane (split path)
+hipError_t launch_u_slots(const float *u, int n, int kp, int d, __hip_bfloat16 *hi,
+                          hipStream_t s);
 
 // ---- Plan applied to column values (plan.hip) ----
 struct PlanJob {
@@ -108,10 +113,15 @@ hipError_t build_padded_layout(const int *perm, const int *off, int k, int *psiz
                                int *scan_sums, hipStream_t s);
 hipError_t fill_padded_layout(const int *perm, const int *off, const int *poff, int k,
                               int *perm_pad, int *blk_cluster, hipStream_t s);
+// Xf: centred FP32 rows; Yhi0/Yhi1: two copies of the hi plane of x - c (one per
+// problem that reads the cloud as columns), slot KP-1 = 1.0; Ylo: the lo plane.
 hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pad,
                               const int *blk_cluster, const float *C, int n_pad, int kp, float *Xf,
-                              __hip_bfloat16 *Yhi, __hip_bfloat16 *Ylo, float *hn, float *lw,
-                              float *wp, hipStream_t s);
+                              __hip_bfloat16 *Yhi0, __hip_bfloat16 *Yhi1, __hip_bfloat16 *Ylo,
+                              float *hn, float *lw, float *wp, hipStream_t s);
+// blk_cent[b * kp + t] = C[blk_cluster[b] * kp + t] for the n_pad / 32 blocks
+hipError_t launch_blk_centroids(const int *blk_cluster, const float *C, int nblk, int kp,
+                                float *blk_cent, hipStream_t s);
 hipError_t launch_unpack_centres(const float *C, int k, int d, int kp, const float *centre,
                                  float *out, hipStream_t s);
 hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, float *out,

@@ -223,7 +223,7 @@ int packed_width(int d) {
 
 int packed_width_bf16(int d) {
     int kp = 16;
-    while (kp < d + 3) kp *= 2;
+    while (kp < d + 4) kp *= 2;
     return kp <= 64 ? kp : 0;
 }
 

@@ -10,13 +10,28 @@
 //                  (FP32, once per    (three bf16 products: hi.hi + hi.lo + lo.hi,
 //                   row and cluster)   FP32 accumulate, error ~ 3 * 2^-16 |x| |dy|)
 //
-// so the split error scales with the cluster radius |dy|, not with |y|; the
-// cluster term is a per-row shift of the running maximum, applied once per
-// cluster.  The column offset u_j (as in the FP32 kernel) is folded into the
-// contraction as three bf16 terms (hi, mid, lo: 24 bits) in slots d, d+1,
-// d+2, against 1.0 in the row's hi plane.  Padding and zero-weight columns use
-// a finite sentinel (-1e30) rather than -inf so that the lo products stay
-// finite (-inf * 0 would be NaN).
+// so the split error scales with the cluster radius |dy|, not with |y|.
+//
+// Three more coordinates ride along in the contraction, so that the matrix
+// cores deliver the exponent itself:
+//   slots d, d+1, d+2 : the column offset u_j as three bf16 terms (hi, mid, lo:
+//                       24 bits) against 1.0 in the row's hi plane;
+//   slot KP-1         : 1.0 in the column's hi plane against w_i split over the
+//                       row's hi and lo planes (16 bits), where w_i ~ shift_i - R_i
+//                       moves the row's running reference R_i into the MFMA
+//                       (shift_i = k <x_i, c_J>).
+// The result is s_ij - R_i with R_i = shift_i - w_i known exactly, and each
+// lane adds 2^{s_ij - R_i} for its 16 columns: one exp2 and one add per pair.
+// Each problem has its own copy of the column hi plane whose slots d..d+2 are
+// rewritten when its column potential changes (k_u_slots), so staging a tile
+// is a plain copy, prefetched into registers one tile ahead.
+// The reference changes only when the cluster changes (same level, re-rounded)
+// or, for the whole wave at once, when a row's sum would leave [2^-60, 2^60)
+// (first mass, overflow, underflow): then the block's maximum sets the new level and the
+// block is re-summed from the accumulators.
+//
+// Padding and zero-weight columns use a finite sentinel (-1e30) rather than
+// -inf so that the lo products stay finite (-inf * 0 would be NaN).
 #include "skh_internal.h"
 
 namespace skh {
@@ -29,15 +44,19 @@ constexpr float kMasked = -1.0e30f;
 static __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 template <int KP>
-__global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
-    constexpr int H = KP / 2;       // dims per lane half
-    constexpr int S = H / 8;        // k-steps of 16 (8 bf16 per lane)
+__global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
+    constexpr int H = KP / 2;        // dims per lane half
+    constexpr int S = H / 8;         // k-steps of 16 (8 bf16 per lane)
     constexpr int RSB = KP * 2 + 16; // LDS row stride in bytes (padding against bank conflicts)
-    constexpr int V16 = KP / 8;     // 16-byte chunks per packed column plane
+    constexpr int V16 = KP / 8;      // 16-byte chunks per packed column plane
+    constexpr int NCH = kColsPerTile * V16 / 256;  // chunks per thread per plane and tile
+    constexpr int NBT = kColsPerTile / 32;         // 32-column blocks per tile
+    constexpr int NCE = NBT * KP;                  // centroid floats per tile
+    static_assert(NCE <= 256, "one centroid float per thread");
     __shared__ __attribute__((aligned(16))) unsigned char lhi[kColsPerTile * RSB];
     __shared__ __attribute__((aligned(16))) unsigned char llo[kColsPerTile * RSB];
-    __shared__ float lcent[kColsPerTile / 32][KP];
-    __shared__ int lcl[kColsPerTile / 32];
+    __shared__ float lcent[NBT][KP];
+    __shared__ int lcl[NBT];
 
     const int wg = blockIdx.x;
     int q = 0;
@@ -49,8 +68,7 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
     const unsigned char *__restrict__ chi = reinterpret_cast<const unsigned char *>(J.cols_hi);
     const unsigned char *__restrict__ clo = reinterpret_cast<const unsigned char *>(J.cols_lo);
     const int *__restrict__ blk_cluster = J.col_blk_cluster;
-    const float *__restrict__ cent = J.col_centroids;
-    const float *__restrict__ u = J.u;
+    const float *__restrict__ blk_cent = J.col_centroids;  // per 32-column block
     float2 *__restrict__ part = J.part;
     const int n_rows = J.n_rows, n_cols = J.n_cols;
     const int local = wg - J.wg_begin;
@@ -112,62 +130,95 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
         }
     }
 
-    float m = -__builtin_huge_valf(), acc_sum = 0.0f, shift = 0.0f;
+    // running reference R (exact: R = shift - w) and the lane's sum relative to it
+    float R = 0.0f, Sl = 0.0f, shift = 0.0f;
     int cur_cluster = -1;
+    // w = w_hi + w_lo (16 significant bits) rides in slot KP-1 of both row planes;
+    // returns the reference the contraction now subtracts
+    auto set_ref = [&](float target) -> float {
+        const __bf16 whi = static_cast<__bf16>(target);
+        const __bf16 wlo = static_cast<__bf16>(target - static_cast<float>(whi));
+        if (h == 1) {
+            xh[S - 1][7] = whi;
+            xl[S - 1][7] = wlo;
+        }
+        return shift - (static_cast<float>(whi) + static_cast<float>(wlo));
+    };
+    R = set_ref(0.0f);
 
-    for (int ri = 0; ri < nranges; ++ri) {
-    if (rng) {
-        const int2 r = rng[ri];
-        c_begin = r.x;
-        c_end = r.y;
-    }
-    for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
-        __syncthreads();
-        for (int e = tid; e < kColsPerTile * V16; e += 256) {
-            const int c = e / V16, v = e - c * V16;
-            const int j = j0 + c;
-            uint4 vh = make_uint4(0u, 0u, 0u, 0u), vl = make_uint4(0u, 0u, 0u, 0u);
-            if (j < c_end) {
-                vh = *reinterpret_cast<const uint4 *>(chi + ((size_t)j * KP + v * 8) * 2);
-                vl = *reinterpret_cast<const uint4 *>(clo + ((size_t)j * KP + v * 8) * 2);
+    // Column tiles, walked range by range; the next tile is loaded into
+    // registers while the current one is computed.  Range ends are multiples
+    // of 32 (clusters are padded), so a 32-column block is either fully inside
+    // the range or skipped.
+    uint4 pfh[NCH], pfl[NCH];
+    float pfc = 0.0f;
+    int pfk = -1;
+    auto next_tile = [&](int &r, int &a, int &e) -> bool {
+        if (r >= 0 && a + kColsPerTile < e) {
+            a += kColsPerTile;
+            return true;
+        }
+        for (++r; r < nranges; ++r) {
+            const int2 v = rng ? rng[r] : make_int2(c_begin, c_end);
+            if (v.x < v.y) {
+                a = v.x;
+                e = v.y;
+                return true;
             }
-            *reinterpret_cast<uint4 *>(lhi + c * RSB + v * 16) = vh;
-            *reinterpret_cast<uint4 *>(llo + c * RSB + v * 16) = vl;
         }
-        if (tid < kColsPerTile / 32) {
-            const int jb0 = j0 + 32 * tid;
-            lcl[tid] = jb0 < c_end ? blk_cluster[jb0 >> 5] : -1;
+        return false;
+    };
+    auto prefetch = [&](int a, int e) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int idx = tid + 256 * k;
+            const int c = idx / V16, v = idx - c * V16;
+            const int j = a + c;
+            pfh[k] = make_uint4(0u, 0u, 0u, 0u);
+            pfl[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (j < e) {
+                pfh[k] = *reinterpret_cast<const uint4 *>(chi + ((size_t)j * KP + v * 8) * 2);
+                pfl[k] = *reinterpret_cast<const uint4 *>(clo + ((size_t)j * KP + v * 8) * 2);
+            }
         }
+        if (tid < NCE) {
+            const int t = tid / KP;
+            pfc = a + 32 * t < e ? blk_cent[(size_t)((a >> 5) + t) * KP + (tid - t * KP)] : 0.0f;
+        }
+        if (tid < NBT) pfk = a + 32 * tid < e ? blk_cluster[(a >> 5) + tid] : -1;
+    };
+
+    int ri = -1, j0 = 0, jend = 0;
+    bool have = next_tile(ri, j0, jend);
+    if (have) prefetch(j0, jend);
+    while (have) {
+        __syncthreads();  // the previous tile is no longer read
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int idx = tid + 256 * k;
+            const int c = idx / V16, v = idx - c * V16;
+            *reinterpret_cast<uint4 *>(lhi + c * RSB + v * 16) = pfh[k];
+            *reinterpret_cast<uint4 *>(llo + c * RSB + v * 16) = pfl[k];
+        }
+        if (tid < NCE) lcent[tid / KP][tid % KP] = pfc;
+        if (tid < NBT) lcl[tid] = pfk;
+        const int cj0 = j0, cend = jend;
+        const bool more = next_tile(ri, j0, jend);
+        if (more) prefetch(j0, jend);
         __syncthreads();
-        if (tid < kColsPerTile) {
-            const int j = j0 + tid;
-            float uu = j < c_end ? u[j] : kMasked;
-            if (!(uu > kMasked)) uu = kMasked;
-            const __bf16 t1 = static_cast<__bf16>(uu);
-            const float r1 = uu - static_cast<float>(t1);
-            const __bf16 t2 = static_cast<__bf16>(r1);
-            const float r2 = r1 - static_cast<float>(t2);
-            const __bf16 t3 = static_cast<__bf16>(r2);
-            __bf16 *slot = reinterpret_cast<__bf16 *>(lhi + tid * RSB) + d;
-            slot[0] = t1;
-            slot[1] = t2;
-            slot[2] = t3;
-        }
-        for (int e = tid; e < (kColsPerTile / 32) * KP; e += 256) {
-            const int t = e / KP, dd = e - t * KP;
-            const int cl = lcl[t];
-            lcent[t][dd] = cl >= 0 ? cent[(size_t)cl * KP + dd] : 0.0f;
-        }
-        __syncthreads();
-        const int nblk = wave_active ? min(kColsPerTile / 32, (c_end - j0 + 31) >> 5) : 0;
+
+        const int nblk = wave_active ? min(NBT, (cend - cj0 + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
             const int cl = lcl[jb];
-            if (cl != cur_cluster) {  // wave-uniform
+            if (cl != cur_cluster) {  // wave-uniform: new cluster shift, same reference level
                 cur_cluster = cl;
                 float r = 0.0f;
 #pragma unroll
                 for (int t = 0; t < H; ++t) r = fmaf(xf[t], lcent[jb][h * H + t], r);
                 shift = r + __shfl_xor(r, 32, 64);
+                const float Rn = set_ref(shift - R);
+                Sl = Sl > 0.0f ? Sl * fast_exp2(R - Rn) : 0.0f;
+                R = Rn;
             }
             v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -181,28 +232,71 @@ __global__ __launch_bounds__(256) void k_softmin_bf16(const SoftminBatch B) {
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh[s], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[s], acc, 0, 0, 0);
             }
-            float tmax = acc[0];
+            // acc[r] = s_ij - R; pairwise sum keeps the add chain short
+            float ex[16];
 #pragma unroll
-            for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
-            if (tmax > 0.5f * kMasked) {
-                const float mn = fmaxf(m, tmax + shift);
-                const float sub = mn - shift;
-                float sblk = 0.0f;
+            for (int r = 0; r < 16; ++r) ex[r] = fast_exp2(acc[r]);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) sblk += fast_exp2(acc[r] - sub);
-                acc_sum = acc_sum * fast_exp2(m - mn) + sblk;
-                m = mn;
+            for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+                for (int r = 0; r < w; ++r) ex[r] += ex[r + w];
+            float Sn = Sl + ex[0];
+            const float Sc = Sn + __shfl_xor(Sn, 32, 64);
+            const bool need = !(Sc < 0x1p60f) || !(Sc >= 0x1p-60f);
+            if (__any(need)) {  // wave-uniform: re-level the rows that need it
+                float tmax = acc[0];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
+                tmax = fmaxf(tmax, __shfl_xor(tmax, 32, 64));
+                const float So = Sl + __shfl_xor(Sl, 32, 64);
+                const float lg = So > 0.0f ? __log2f(So) : -__builtin_huge_valf();
+                const float top = fmaxf(tmax, lg);  // new level relative to R
+                if (need && top > 0.5f * kMasked) {
+                    const float Rn = set_ref(shift - (R + top));
+                    const float dl = R - Rn;
+                    float sb = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) sb += fast_exp2(acc[r] + dl);
+                    Sn = (Sl > 0.0f ? Sl * fast_exp2(dl) : 0.0f) + sb;
+                    R = Rn;
+                }
             }
+            Sl = Sn;
         }
-    }
+        have = more;
     }
 
-    const float m2 = __shfl_xor(m, 32, 64);
-    const float s2 = __shfl_xor(acc_sum, 32, 64);
-    const float M = fmaxf(m, m2);
-    float Ssum = 0.0f;
-    if (M > -__builtin_huge_valf()) Ssum = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
-    if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, Ssum);
+    // both lane halves of a row share R: the row's partial is (R, sum of both halves)
+    const float Sr = Sl + __shfl_xor(Sl, 32, 64);
+    const float M = Sr > 0.0f ? R : -__builtin_huge_valf();
+    if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, Sr);
+}
+
+// Column offsets u_j into slots d, d+1, d+2 of a packed hi plane, as three bf16
+// terms (hi, mid, lo); non-finite or very negative offsets (no mass) become the
+// finite sentinel.
+__global__ __launch_bounds__(256) void k_u_slots(const float *__restrict__ u, int n, int kp, int d,
+                                                 __hip_bfloat16 *__restrict__ hi) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float uu = u[i];
+    if (!(uu > kMasked)) uu = kMasked;
+    const __bf16 t1 = static_cast<__bf16>(uu);
+    const float r1 = uu - static_cast<float>(t1);
+    const __bf16 t2 = static_cast<__bf16>(r1);
+    const float r2 = r1 - static_cast<float>(t2);
+    const __bf16 t3 = static_cast<__bf16>(r2);
+    __bf16 *row = reinterpret_cast<__bf16 *>(hi) + (size_t)i * kp;
+    row[d] = t1;
+    row[d + 1] = t2;
+    row[d + 2] = t3;
+}
+
+hipError_t launch_u_slots(const float *u, int n, int kp, int d, __hip_bfloat16 *hi,
+                          hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_u_slots, dim3((n + 255) / 256), dim3(256), 0, s, u, n, kp, d, hi);
+    return hipGetLastError();
 }
 
 hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s) {

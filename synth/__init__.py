@@ -44,19 +44,32 @@ def _bezier(ctrl: np.ndarray, t: np.ndarray) -> np.ndarray:
     """Cubic Bezier curves. ctrl: (F, 4, 3); t: (T,) -> (F, T, 3)."""
     s = 1.0 - t
     basis = np.stack([s ** 3, 3 * s * s * t, 3 * s * t * t, t ** 3], axis=1)  # (T, 4)
-    return np.einsum("tk,fkc->ftc", basis, ctrl)
+    F = ctrl.shape[0]
+    flat = np.ascontiguousarray(ctrl.transpose(0, 2, 1)).reshape(F * 3, 4) @ basis.T  # (3F, T)
+    return flat.reshape(F, 3, -1).transpose(0, 2, 1)
 
 
 def _resample_equal_arclength(poly: np.ndarray, P: int) -> np.ndarray:
-    """Resample polylines (F, T, 3) to P points equally spaced in arc length (both ends kept)."""
+    """Resample polylines (F, T, 3) to P points equally spaced in arc length (both ends kept).
+
+    Target k of a fibre lies on the segment [idx, idx + 1] with idx the last
+    sample whose cumulative length is <= the target (clipped to the last
+    segment), and is interpolated linearly on that segment."""
     F, T, _ = poly.shape
-    seg = np.linalg.norm(np.diff(poly, axis=1), axis=2)
+    dif = np.diff(poly, axis=1)
+    seg = np.sqrt(np.sum(dif * dif, axis=2))
     cum = np.concatenate([np.zeros((F, 1)), np.cumsum(seg, axis=1)], axis=1)  # (F, T)
     targets = cum[:, -1:] * np.linspace(0.0, 1.0, P)[None, :]  # (F, P)
-    # searchsorted per row: count of cum <= target, minus one
-    idx = (cum[:, None, :] <= targets[:, :, None]).sum(axis=2) - 1
-    idx = np.clip(idx, 0, T - 2)
+    # one sorted search over all fibres (row offsets keep rows apart), then an
+    # exact fix-up against the unshifted lengths
+    span = 2.0 * cum[:, -1].max() + 1.0
+    shift = np.arange(F, dtype=np.float64)[:, None] * span
+    pos = np.searchsorted((cum + shift).ravel(), (targets + shift).ravel(), side="right")
+    idx = np.clip(pos.reshape(F, P) - 1 - np.arange(F)[:, None] * T, 0, T - 2)
     rows = np.arange(F)[:, None]
+    for _ in range(3):
+        idx = idx + ((idx < T - 2) & (cum[rows, np.minimum(idx + 1, T - 1)] <= targets))
+        idx = idx - ((idx > 0) & (cum[rows, idx] > targets))
     c0, c1 = cum[rows, idx], cum[rows, idx + 1]
     den = np.where(c1 > c0, c1 - c0, 1.0)
     w = np.where(c1 > c0, (targets - c0) / den, 0.0)

@@ -65,9 +65,12 @@ def test_full_multiscale_converges_to_dense_fixed_point(precision):
     assert st["converged"] == 1 and std["converged"] == 1
     assert st["coarse_iters"] > 0
     assert S == pytest.approx(Sd, rel=1e-5 if precision == "fp32" else 1e-3)
-    # unbalanced potentials are unique: compare them too
-    scale = max(1.0, np.abs(potd["f"]).max())
-    np.testing.assert_allclose(pot["f"], potd["f"], atol=(1e-4 if precision == "fp32" else 1e-2) * scale)
+    # At a marginal tolerance tol the unbalanced potentials are pinned only up to
+    # near-gauge shifts of about rho * tol (the e^{-f/rho} restoring term), per weakly
+    # coupled group of points (here: per bundle), so only that bound is checked.
+    rho, tol = 20.0 ** 2, 1e-4
+    assert np.abs(pot["f"] - potd["f"]).max() <= 4 * rho * tol
+    assert np.abs(pot["g"] - potd["g"]).max() <= 4 * rho * tol
 
 
 def test_multiscale_blob_config_balanced():

@@ -114,7 +114,7 @@ def _check_bf16(x, y, w, h, eps, lam, tag):
     return err
 
 
-@pytest.mark.parametrize("n,m,d", [(300, 517, 3), (1000, 1300, 60), (257, 4000, 16), (33, 2500, 61),
+@pytest.mark.parametrize("n,m,d", [(300, 517, 3), (1000, 1300, 60), (257, 4000, 16), (33, 2500, 60),
                                    (5, 7, 1), (640, 64, 29)])
 @pytest.mark.parametrize("eps_rel", [1e-2, 1.0])
 def test_softmin_bf16_matches_oracle(n, m, d, eps_rel):
@@ -135,7 +135,27 @@ def test_softmin_bf16_fibres_is_close_to_fp32_accuracy():
 
 def test_softmin_bf16_rejects_wide_points():
     import paper_2107_02010_amd as skh
-    x, y, w, h = _case(10, 10, 62, seed=1)
-    note("softmin bf16 d=62")
-    with pytest.raises(skh.SkhError):
-        skh.softmin(cuda(x), cuda(y), cuda(w), cuda(h), 1.0, precision="bf16x3")
+    for d in (61, 62):
+        x, y, w, h = _case(10, 10, d, seed=1)
+        note(f"softmin bf16 d={d}")
+        with pytest.raises(skh.SkhError):
+            skh.softmin(cuda(x), cuda(y), cuda(w), cuda(h), 1.0, precision="bf16x3")
+
+
+def test_softmin_bf16_no_mass_and_far_clusters():
+    # zero weights (no mass: +inf), and far-apart clusters with a tiny eps, so the
+    # running reference must be re-levelled many times inside a row's sweep
+    import paper_2107_02010_amd as skh
+    x, y, w, h = _case(40, 300, 8, seed=5)
+    note("softmin bf16 zero weights")
+    out = host(skh.softmin(cuda(x), cuda(y), cuda(np.zeros_like(w)), cuda(h), 0.5,
+                           precision="bf16x3"))
+    assert np.all(np.isinf(out)) and np.all(out > 0)
+    rng = np.random.default_rng(7)
+    centres = rng.uniform(-50, 50, size=(12, 8))
+    y = (centres[rng.integers(0, 12, 3000)] + rng.standard_normal((3000, 8))).astype(np.float32)
+    x = (centres[rng.integers(0, 12, 700)] + rng.standard_normal((700, 8))).astype(np.float32)
+    w = synth.random_weights(3000, 8)
+    h = (20.0 * rng.standard_normal(3000)).astype(np.float32)
+    for eps in (0.05, 3.0):
+        _check_bf16(x, y, w, h, eps, 1.0, "far-clusters")
