@@ -51,6 +51,15 @@ enum {
  * in both modes. */
 enum { SKH_FP32 = 0, SKH_BF16_SPLIT = 1 };
 
+/* skh_params.init: where the dual vectors start. */
+enum {
+    SKH_INIT_COLD = 0,  /* zero, at the largest scale (the Algorithm's start) */
+    SKH_INIT_GIVEN = 1, /* f, g, p, q hold starting values */
+    SKH_INIT_WARM = 2   /* as GIVEN, but checked first: if any value is NaN or
+                           infinite they are discarded and the call runs cold
+                           (stats.warm_fallback = 1) */
+};
+
 typedef struct skh_ctx skh_ctx;
 
 /* Solver parameters (the Algorithm's parameter lines and the two run modes). */
@@ -64,11 +73,14 @@ typedef struct skh_params {
                             0: the mass-weighted RMS cluster radius; < 0: no coarse phase */
     double trunc_theta;  /* multiscale: keep cluster blocks whose weight bound is >= e^{-theta};
                             <= 0: keep every block */
+    double start_scale;  /* init != COLD: largest scale of the schedule (start_scale q^k, then
+                            blur); <= 0: the diameter rule.  A cold run ignores it */
     int32_t extra_iters; /* iterations at sigma = blur after the scale list (>= 0) */
     int32_t max_iters;   /* converged mode: at most this many iterations after the list */
     int32_t check_every; /* converged mode: marginal-error check period (>= 1) */
     int32_t precision;   /* SKH_FP32 or SKH_BF16_SPLIT */
-    int32_t init;        /* nonzero: f, g, p, q hold starting values (warm start) */
+    int32_t init;        /* SKH_INIT_COLD, SKH_INIT_GIVEN or SKH_INIT_WARM; a given start
+                            skips the multiscale coarse phase */
     int32_t timing;      /* nonzero: time every softmin launch with HIP events (skh_stats) */
     int32_t multiscale;  /* nonzero: K-means coarse phase + cluster-block truncation */
     int32_t n_clusters;  /* multiscale / split path: clusters per cloud; 0: ceil(sqrt(n)) */
@@ -84,7 +96,8 @@ typedef struct skh_stats {
     int32_t checks;      /* number of marginal-error checks (each one host sync) */
     int32_t softmin_launches; /* softmin kernel launches (one per iteration) */
     int32_t coarse_iters;/* multiscale: iterations on the coarse (K-means) clouds */
-    int32_t reserved_i[2];
+    int32_t warm_fallback;/* SKH_INIT_WARM: the starting values were not finite, ran cold */
+    int32_t reserved_i[1];
     double diameter;     /* largest scale used */
     double eps;          /* eps of the last iteration */
     double marginal_err; /* last measured relative L1 marginal error (max of the four problems) */
@@ -98,8 +111,8 @@ typedef struct skh_stats {
 /* Fills *p with blur = 0.05, reach = +inf (balanced), scaling = 0.9,
  * diameter = 0 (auto), tol = 0 (schedule mode), extra_iters = 0,
  * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0,
- * multiscale = 0, jump_scale = 0, trunc_theta = 20, n_clusters = 0,
- * kmeans_iters = 10. */
+ * multiscale = 0, jump_scale = 0, trunc_theta = 20, start_scale = 0,
+ * n_clusters = 0, kmeans_iters = 10. */
 void skh_params_default(skh_params *p);
 
 /* Creates a context on HIP device `device` bound to stream `hip_stream`
@@ -134,7 +147,8 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
  *   f (n): b^{beta->alpha}, g (m): a^{alpha->beta},
  *   p (n): a^{alpha<->alpha}, q (m): b^{beta<->beta}  (device, FP32).
  * When params->init is nonzero, f, g, p, q must be given and hold the
- * starting values.  Returns SKH_OK, SKH_NOT_CONVERGED (converged mode only),
+ * starting values (caller order); the schedule then starts at
+ * params->start_scale.  Returns SKH_OK, SKH_NOT_CONVERGED (converged mode only),
  * or an error.  Weights must be >= 0 and not all zero; coordinates finite.
  */
 int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_t n,
@@ -189,6 +203,77 @@ int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const fl
 int skh_kmeans(skh_ctx *ctx, const float *x, const float *w, int64_t n, int32_t d, int32_t k,
                int32_t iters, float *centres, float *masses, int32_t *labels, int32_t *perm,
                int32_t *offsets);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper's method: a set encoder that
+ * predicts, for every K-means cluster of the two clouds (the coarse scale of
+ * Section 2's coarse-to-fine strategy), the cluster's mean cross dual and
+ * self dual divided by blur^2.  Broadcast to the points, the predictions are
+ * starting values for skh_sinkhorn_divergence (init = SKH_INIT_WARM), whose
+ * Algorithm then runs from start_scale to blur and decides the fixed point.
+ *
+ * Tokens (SKH_WS_IN = 64 features per cluster c of one cloud):
+ *   [ (centre_c - mu) / diam  (d values, zeros up to index 59),
+ *     log(k m_c / M), r_c / diam, [alpha side], [beta side] ]
+ * with mu the centre and diam the diagonal of the joint bounding box of x and
+ * y, m_c the cluster's mass, M the cloud's mass, k its cluster count and r_c
+ * the largest distance of a member to the centre.  Token weight m_c.
+ * d <= 60.
+ *
+ * Network: parameters theta = one FP32 vector of SKH_WS_N_PARAMS values,
+ * in order W1 (256 x 64), b1, W2 (256 x 256), b2, W3 (256 x 256), b3,
+ * W4 (256 x 768), b4, W5 (2 x 256), b5 (weights row-major, out x in).
+ *   h = relu(relu(relu(X W1^T + b1) W2^T + b2) W3^T + b3)
+ *   P_alpha, P_beta: token-weighted means of h over each cloud of a pair
+ *   y_t = relu([h_t, P_alpha, P_beta] W4^T + b4) W5^T + b5    (2 values)
+ * Batches: n_pairs cloud pairs, tokens in order pair 0 alpha, pair 0 beta,
+ * pair 1 alpha, ...; seg (HOST array, 2 n_pairs + 1 offsets, seg[0] = 0,
+ * non-decreasing, every segment non-empty) delimits them; T = seg[2 n_pairs].
+ * Loss (training): mean over pairs of sum_t (w_t / W_pair) |y_t - target_t|^2.
+ * ------------------------------------------------------------------------- */
+#define SKH_WS_IN 64
+#define SKH_WS_WIDTH 256
+#define SKH_WS_OUT 2
+#define SKH_WS_N_PARAMS 345602
+#define SKH_WS_MAX_PAIRS 256
+
+/* Tokens of the pair (alpha, beta): K-means of each cloud exactly as the
+ * multiscale solver clusters it (k = n_clusters, or ceil(sqrt(n)) when 0, at
+ * most 4096; kmeans_iters Lloyd iterations).  Writes tokens (kx + ky rows of
+ * 64, alpha clusters first), tok_w (kx + ky), labels_x (n), labels_y (m) and
+ * k_out[0] = kx, k_out[1] = ky (host).  cap_tokens: rows available in tokens
+ * (SKH_EINVAL when kx + ky exceeds it).  Synchronises the stream. */
+int skh_ws_tokens(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                  const float *b, int64_t m, int32_t d, int32_t n_clusters, int32_t kmeans_iters,
+                  int32_t cap_tokens, float *tokens, float *tok_w, int32_t *labels_x,
+                  int32_t *labels_y, int32_t *k_out);
+
+/* Network forward on a batch: out (T x 2).  precision SKH_FP32 or
+ * SKH_BF16_SPLIT (dense layers on bfloat16 operands, FP32 accumulation). */
+int skh_ws_forward(skh_ctx *ctx, const float *theta, int32_t n_pairs, const int32_t *seg,
+                   const float *tokens, const float *tok_w, int32_t precision, float *out);
+
+/* Loss (host, FP64 sum) and its gradient grad (SKH_WS_N_PARAMS, device) for
+ * targets (T x 2); FP32 forward and backward.  Synchronises the stream. */
+int skh_ws_loss_grad(skh_ctx *ctx, const float *theta, int32_t n_pairs, const int32_t *seg,
+                     const float *tokens, const float *tok_w, const float *target, double *loss,
+                     float *grad);
+
+/* One Adam update (Kingma & Ba, bias-corrected; step >= 1) of theta with
+ * moments m and v (n values each, device). */
+int skh_ws_adam(skh_ctx *ctx, int64_t n, float *theta, const float *grad, float *m, float *v,
+                int32_t step, double lr, double beta1, double beta2, double eps);
+
+/* Training targets of one cloud: out[c] = (scale * mean of pot_cross,
+ * scale * mean of pot_self) over the points with label c, weighted by w
+ * (FP64 sums in point order; 0 for a massless cluster).  labels in [0, k). */
+int skh_ws_targets(skh_ctx *ctx, const int32_t *labels, int64_t n, int32_t k, const float *w,
+                   const float *pot_cross, const float *pot_self, double scale, float *out);
+
+/* Starting values of one cloud from the predictions pred (k x 2):
+ * pot_cross[i] = scale pred[labels[i]][0], pot_self[i] = scale pred[labels[i]][1]. */
+int skh_ws_expand(skh_ctx *ctx, const int32_t *labels, int64_t n, int32_t k, const float *pred,
+                  double scale, float *pot_cross, float *pot_self);
 
 #ifdef __cplusplus
 }

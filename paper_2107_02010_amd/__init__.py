@@ -94,12 +94,15 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
                         max_iters: int = 1000, check_every: int = 5, precision: str = "fp32",
                         init=None, potentials: bool = False, timing: bool = False,
                         multiscale: bool = False, jump_scale: float = 0.0,
-                        trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10):
+                        trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10,
+                        start_scale: float = 0.0, checked_init: bool = False):
     """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
 
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
     tol > 0 selects converged mode (iterate at blur until the marginal error <= tol).
-    init: optional (f, g, p, q) starting potentials.  With potentials=True returns
+    init: optional (f, g, p, q) starting potentials; the schedule then starts at start_scale
+    (<= 0: the diameter rule).  checked_init=True: non-finite starting values are discarded
+    and the call runs cold (stats["warm_fallback"] = 1).  With potentials=True returns
     (S, dict(f=..., g=..., p=..., q=...), stats dict), else S (a Python float).
     timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
     multiscale=True: K-means coarse phase while sigma > jump_scale (0: RMS cluster radius,
@@ -131,7 +134,8 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     if init is not None:
         f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in
                       zip(init, (n, m, n, m), ("f", "g", "p", "q")))
-        P.init = 1
+        P.init = _lib.SKH_INIT_WARM if checked_init else _lib.SKH_INIT_GIVEN
+        P.start_scale = float(start_scale)
     else:
         f = torch.empty(n, dtype=torch.float32, device=dev)
         g = torch.empty(m, dtype=torch.float32, device=dev)

@@ -22,6 +22,14 @@ SKH_ENONFINITE = -4
 SKH_FP32 = 0
 SKH_BF16_SPLIT = 1
 SKH_MAX_DIM = 63
+SKH_INIT_COLD = 0
+SKH_INIT_GIVEN = 1
+SKH_INIT_WARM = 2
+SKH_WS_IN = 64
+SKH_WS_WIDTH = 256
+SKH_WS_OUT = 2
+SKH_WS_N_PARAMS = 345602
+SKH_WS_MAX_PAIRS = 256
 
 _c_i32, _c_i64, _c_d, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -29,7 +37,7 @@ _c_i32, _c_i64, _c_d, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, c
 class SkhParams(ctypes.Structure):
     _fields_ = [
         ("blur", _c_d), ("reach", _c_d), ("scaling", _c_d), ("diameter", _c_d), ("tol", _c_d),
-        ("jump_scale", _c_d), ("trunc_theta", _c_d),
+        ("jump_scale", _c_d), ("trunc_theta", _c_d), ("start_scale", _c_d),
         ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
         ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("multiscale", _c_i32),
         ("n_clusters", _c_i32), ("kmeans_iters", _c_i32), ("reserved", _c_i32 * 5),
@@ -39,7 +47,8 @@ class SkhParams(ctypes.Structure):
 class SkhStats(ctypes.Structure):
     _fields_ = [
         ("iters", _c_i32), ("n_scales", _c_i32), ("converged", _c_i32), ("checks", _c_i32),
-        ("softmin_launches", _c_i32), ("coarse_iters", _c_i32), ("reserved_i", _c_i32 * 2),
+        ("softmin_launches", _c_i32), ("coarse_iters", _c_i32), ("warm_fallback", _c_i32),
+        ("reserved_i", _c_i32 * 1),
         ("diameter", _c_d), ("eps", _c_d), ("marginal_err", _c_d), ("pairs", _c_d),
         ("ms_total", _c_d), ("ms_softmin", _c_d), ("dense_pairs", _c_d), ("reserved", _c_d * 1),
     ]
@@ -72,6 +81,17 @@ SIGNATURES = {
                             _c_vp, _c_d, _c_vp]),
     "skh_kmeans": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp,
                             _c_vp, _c_vp, _c_vp]),
+    "skh_ws_tokens": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_i32,
+                               _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp,
+                               ctypes.POINTER(_c_i32)]),
+    "skh_ws_forward": (_c_i32, [_c_vp, _c_vp, _c_i32, ctypes.POINTER(_c_i32), _c_vp, _c_vp, _c_i32,
+                                _c_vp]),
+    "skh_ws_loss_grad": (_c_i32, [_c_vp, _c_vp, _c_i32, ctypes.POINTER(_c_i32), _c_vp, _c_vp,
+                                  _c_vp, ctypes.POINTER(_c_d), _c_vp]),
+    "skh_ws_adam": (_c_i32, [_c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_d, _c_d, _c_d,
+                             _c_d]),
+    "skh_ws_targets": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _c_vp, _c_d, _c_vp]),
+    "skh_ws_expand": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp, _c_d, _c_vp, _c_vp]),
 }
 
 _lib = None

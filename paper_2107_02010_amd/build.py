@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libskh.so")
 
 SOURCES = ["softmin.hip", "softmin_bf16.hip", "plan.hip", "kmeans.hip", "multiscale.hip",
-           "aux_kernels.hip", "api.cpp"]
+           "aux_kernels.hip", "warmstart.hip", "api.cpp", "ws_api.cpp"]
 ARCH = os.environ.get("SKH_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code; hipcc's host

@@ -17,128 +17,13 @@
 
 #include "skh.h"
 #include "skh_internal.h"
+#include "host_util.h"
 
-struct skh_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    void *ws[2] = {nullptr, nullptr};  // setup buffers, loop buffers
-    size_t ws_bytes[2] = {0, 0};
-    void *host = nullptr;  // pinned, kHostBytes
-    int num_cus = 256;
-    std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches
-    std::string err;
-};
-
-namespace {
-
-constexpr size_t kHostBytes = 4096;
 thread_local std::string g_create_err;
 
-int fail(skh_ctx *c, int code, const std::string &msg) {
-    if (c) c->err = msg;
-    return code;
-}
+namespace {
+using namespace skh_host;
 
-#define SKH_HIP(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(ctx, SKH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-// Sub-allocates one workspace; a first pass with base == nullptr measures.
-struct Carver {
-    char *base;
-    size_t off = 0;
-    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
-    template <class T>
-    T *take(size_t count) {
-        off = (off + 255) & ~size_t(255);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
-
-int ensure_ws(skh_ctx *ctx, int slot, size_t bytes) {
-    if (bytes <= ctx->ws_bytes[slot]) return SKH_OK;
-    SKH_HIP(hipStreamSynchronize(ctx->stream));
-    if (ctx->ws[slot]) {
-        SKH_HIP(hipFree(ctx->ws[slot]));
-        ctx->ws[slot] = nullptr;
-        ctx->ws_bytes[slot] = 0;
-    }
-    size_t want = bytes + bytes / 8;
-    if (hipMalloc(&ctx->ws[slot], want) != hipSuccess) {
-        (void)hipGetLastError();
-        ctx->ws[slot] = nullptr;
-        return fail(ctx, SKH_ENOMEM,
-                    "workspace allocation of " + std::to_string(want) + " bytes failed");
-    }
-    ctx->ws_bytes[slot] = want;
-    return SKH_OK;
-}
-
-bool is_balanced(double reach) { return !(reach > 0.0) || std::isinf(reach); }
-
-// lambda of the Algorithm, 1 / (1 + (sigma / reach)^2).
-double damping(double sigma, double reach) {
-    if (is_balanced(reach)) return 1.0;
-    const double t = sigma / reach;
-    return 1.0 / (1.0 + t * t);
-}
-
-// The scale list [d, d q, ..., blur] of the Algorithm's loop header:
-// d q^k for k < K = ceil(log(d / blur) / log(1 / q)), then blur; [blur] when d <= blur.
-std::vector<double> scale_list(double diameter, double blur, double scaling) {
-    std::vector<double> s;
-    if (!(diameter > blur)) {
-        s.push_back(blur);
-        return s;
-    }
-    const int K = (int)std::ceil(std::log(diameter / blur) / std::log(1.0 / scaling));
-    for (int k = 0; k < K; ++k) s.push_back(diameter * std::pow(scaling, (double)k));
-    s.push_back(blur);
-    return s;
-}
-
-int target_wgs(const skh_ctx *ctx) { return ctx->num_cus * 8; }
-
-int ensure_events(skh_ctx *ctx, size_t count) {
-    while (ctx->events.size() < count) {
-        hipEvent_t e;
-        SKH_HIP(hipEventCreate(&e));
-        ctx->events.push_back(e);
-    }
-    return SKH_OK;
-}
-
-constexpr double kLog2e = 1.4426950408889634074;
-constexpr int64_t kMaxPoints = 1 << 28;
-constexpr int kKmeansIters = 10;
-constexpr int kRowTile = skh::kRowsPerBlock;
-
-// Number of K-means clusters for n points: ceil(sqrt(n)), at most 4096.
-int kmeans_k(int64_t n) {
-    int k = (int)std::ceil(std::sqrt((double)n));
-    if (k < 1) k = 1;
-    if (k > 4096) k = 4096;
-    return k;
-}
-
-// Device buffers of one cloud in the cluster-sorted, 32-padded layout.
 struct Clustered {
     int n = 0, k = 0, n_pad_max = 0, n_pad = 0, max_tiles = 0, n_tiles = 0;
     float *C = nullptr, *cmass = nullptr, *radius = nullptr;  // k x kp, k, k
@@ -229,6 +114,7 @@ void skh_params_default(skh_params *p) {
     p->multiscale = 0;
     p->jump_scale = 0.0;
     p->trunc_theta = 20.0;
+    p->start_scale = 0.0;
     p->n_clusters = 0;
     p->kmeans_iters = kKmeansIters;
 }
@@ -265,7 +151,7 @@ void skh_destroy(skh_ctx *ctx) {
     {
         DeviceGuard guard(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < 3; ++k)
             if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
         if (ctx->host) (void)hipHostFree(ctx->host);
         for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -402,7 +288,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (n < 1 || m < 1) return fail(ctx, SKH_EINVAL, "n and m must be >= 1");
     if (n > kMaxPoints || m > kMaxPoints) return fail(ctx, SKH_EINVAL, "n or m too large");
     if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
-    const skh_params P = *params;
+    skh_params P = *params;
     if (!(P.blur > 0.0) || !std::isfinite(P.blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
     if (!(P.scaling > 0.0 && P.scaling < 1.0))
         return fail(ctx, SKH_EINVAL, "scaling must be in (0, 1)");
@@ -415,6 +301,9 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         return fail(ctx, SKH_EINVAL, "unknown precision");
     for (int k = 0; k < 5; ++k)
         if (P.reserved[k]) return fail(ctx, SKH_EINVAL, "reserved params must be zero");
+    if (P.init != SKH_INIT_COLD && P.init != SKH_INIT_GIVEN && P.init != SKH_INIT_WARM)
+        return fail(ctx, SKH_EINVAL, "unknown init mode");
+    if (std::isnan(P.start_scale)) return fail(ctx, SKH_EINVAL, "NaN parameter");
     if (P.init && (!f || !g || !p || !q))
         return fail(ctx, SKH_EINVAL, "init requires f, g, p and q");
     const bool split = P.precision == SKH_BF16_SPLIT;
@@ -434,7 +323,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     float *Xp, *Yp, *hnx, *hny, *lwx, *lwy, *plo, *phi, *lohi;
     float *dist[4] = {nullptr, nullptr, nullptr, nullptr};  // xx, yy, yx, xy
     double *pmass, *mass;
-    int *pbad, *bad;
+    int *pbad, *bad, *wbad;
     Clustered cx, cy;
     for (int pass = 0; pass < 2; ++pass) {
         Carver c(pass ? ctx->ws[0] : nullptr);
@@ -451,6 +340,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         lohi = c.take<float>(192);
         mass = c.take<double>(2);
         bad = c.take<int>(4);
+        wbad = c.take<int>(1);
         if (clustered) {
             cx.carve(c, (int)n, kp, P.n_clusters);
             cy.carve(c, (int)m, kp, P.n_clusters);
@@ -474,7 +364,20 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     SKH_HIP(hipMemcpyAsync(hb, lohi, 128 * sizeof(float), hipMemcpyDeviceToHost, s));
     SKH_HIP(hipMemcpyAsync(hb + 512, mass, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     SKH_HIP(hipMemcpyAsync(hb + 528, bad, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (P.init == SKH_INIT_WARM) {  // the checked start: every starting value must be finite
+        SKH_HIP(hipMemsetAsync(wbad, 0, sizeof(int), s));
+        SKH_HIP(skh::launch_nonfinite(f, n, wbad, s));
+        SKH_HIP(skh::launch_nonfinite(g, m, wbad, s));
+        SKH_HIP(skh::launch_nonfinite(p, n, wbad, s));
+        SKH_HIP(skh::launch_nonfinite(q, m, wbad, s));
+        SKH_HIP(hipMemcpyAsync(hb + 544, wbad, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     SKH_HIP(hipStreamSynchronize(s));
+    int warm_fallback = 0;
+    if (P.init == SKH_INIT_WARM && *reinterpret_cast<const int *>(hb + 544)) {
+        P.init = SKH_INIT_COLD;
+        warm_fallback = 1;
+    }
     const float *hlo = reinterpret_cast<const float *>(hb);
     const float *hhi = hlo + 64;
     const double *hmass = reinterpret_cast<const double *>(hb + 512);
@@ -484,7 +387,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (!(hmass[0] > 0.0) || !(hmass[1] > 0.0))
         return fail(ctx, SKH_EINVAL, "total weight must be positive");
 
-    double diam = P.diameter;
+    double diam = P.init && P.start_scale > 0.0 ? P.start_scale : P.diameter;
     if (!(diam > 0.0)) {
         double s2 = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -931,6 +834,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         stats->converged = converged ? 1 : 0;
         stats->checks = checks;
         stats->diameter = diam;
+        stats->warm_fallback = warm_fallback;
         stats->eps = eps;
         stats->marginal_err = err;
         stats->pairs = pairs;

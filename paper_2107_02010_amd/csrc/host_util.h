@@ -1,0 +1,135 @@
+// Host-side context and helpers shared by the C-ABI translation units of libskh.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "skh.h"
+#include "skh_internal.h"
+
+struct skh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *ws[3] = {nullptr, nullptr, nullptr};  // setup, loop, warm-start network buffers
+    size_t ws_bytes[3] = {0, 0, 0};
+    void *host = nullptr;  // pinned, kHostBytes
+    int num_cus = 256;
+    std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches
+    std::string err;
+};
+
+namespace skh_host {
+
+constexpr size_t kHostBytes = 4096;
+
+inline int fail(skh_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define SKH_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ctx, SKH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Sub-allocates one workspace; a first pass with base == nullptr measures.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+inline int ensure_ws(skh_ctx *ctx, int slot, size_t bytes) {
+    if (bytes <= ctx->ws_bytes[slot]) return SKH_OK;
+    SKH_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->ws[slot]) {
+        SKH_HIP(hipFree(ctx->ws[slot]));
+        ctx->ws[slot] = nullptr;
+        ctx->ws_bytes[slot] = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&ctx->ws[slot], want) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->ws[slot] = nullptr;
+        return fail(ctx, SKH_ENOMEM,
+                    "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->ws_bytes[slot] = want;
+    return SKH_OK;
+}
+
+inline bool is_balanced(double reach) { return !(reach > 0.0) || std::isinf(reach); }
+
+// lambda of the Algorithm, 1 / (1 + (sigma / reach)^2).
+inline double damping(double sigma, double reach) {
+    if (is_balanced(reach)) return 1.0;
+    const double t = sigma / reach;
+    return 1.0 / (1.0 + t * t);
+}
+
+// The scale list [d, d q, ..., blur] of the Algorithm's loop header:
+// d q^k for k < K = ceil(log(d / blur) / log(1 / q)), then blur; [blur] when d <= blur.
+inline std::vector<double> scale_list(double diameter, double blur, double scaling) {
+    std::vector<double> s;
+    if (!(diameter > blur)) {
+        s.push_back(blur);
+        return s;
+    }
+    const int K = (int)std::ceil(std::log(diameter / blur) / std::log(1.0 / scaling));
+    for (int k = 0; k < K; ++k) s.push_back(diameter * std::pow(scaling, (double)k));
+    s.push_back(blur);
+    return s;
+}
+
+inline int target_wgs(const skh_ctx *ctx) { return ctx->num_cus * 8; }
+
+inline int ensure_events(skh_ctx *ctx, size_t count) {
+    while (ctx->events.size() < count) {
+        hipEvent_t e;
+        SKH_HIP(hipEventCreate(&e));
+        ctx->events.push_back(e);
+    }
+    return SKH_OK;
+}
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int64_t kMaxPoints = 1 << 28;
+constexpr int kKmeansIters = 10;
+constexpr int kRowTile = skh::kRowsPerBlock;
+
+// Number of K-means clusters for n points: ceil(sqrt(n)), at most 4096.
+inline int kmeans_k(int64_t n) {
+    int k = (int)std::ceil(std::sqrt((double)n));
+    if (k < 1) k = 1;
+    if (k > 4096) k = 4096;
+    return k;
+}
+
+// Device buffers of one cloud in the cluster-sorted, 32-padded layout.
+
+}  // namespace skh_host

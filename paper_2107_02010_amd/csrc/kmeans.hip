@@ -456,3 +456,42 @@ hipError_t launch_permute(const float *src, const int *perm_pad, int n_pad, floa
 }
 
 }  // namespace skh
+
+namespace skh {
+
+// Labels in [0, k) check: *bad |= 1 for any label out of range.
+__global__ __launch_bounds__(kT) void k_check_labels(const int *__restrict__ lab, int n, int k,
+                                                     int *__restrict__ bad) {
+    const int i = blockIdx.x * kT + threadIdx.x;
+    const int b = i < n && (lab[i] < 0 || lab[i] >= k);
+    if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_labels(const int *lab, int n, int k, int *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_labels, dim3(blocks(n)), dim3(kT), 0, s, lab, n, k, bad);
+    return hipGetLastError();
+}
+
+// Stable counting sort of labels already in ws[0, n) (the K-means workspace
+// layout): perm (sorted position -> point) and off (k + 1).
+hipError_t sort_labels(int n, int k, int *ws, int **perm_out, int **off_out, hipStream_t s) {
+    const int nb = (n + kT - 1) / kT;
+    const int64_t len = (int64_t)k * nb;
+    int *label = ws;
+    int *slabel = label + n;
+    int *perm = slabel + n;
+    int *counts = perm + n;
+    int *offs = counts + len;
+    int *sums = offs + len;
+    int *off = sums + scan_sums_len(len);
+    hipLaunchKernelGGL(k_label_count, dim3(nb), dim3(kT), k * sizeof(int), s, label, n, k, nb, counts);
+    hipError_t e = launch_exclusive_scan(counts, len, sums, offs, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_label_scatter, dim3(nb), dim3(kT), 0, s, label, n, nb, offs, perm, slabel);
+    hipLaunchKernelGGL(k_cluster_offsets, dim3(blocks(k + 1)), dim3(kT), 0, s, offs, k, nb, n, off);
+    *perm_out = perm;
+    *off_out = off;
+    return hipGetLastError();
+}
+
+}  // namespace skh

@@ -200,4 +200,55 @@ hipError_t launch_divergence_terms(const float *a, const float *f, const float *
                                    double rho, int balanced, double *part, int *nb_out,
                                    hipStream_t s);
 
+// ---- Learned warm start (set encoder over K-means cluster tokens) ----
+constexpr int kWsIn = 64;      // token features
+constexpr int kWsWidth = 256;  // hidden width
+constexpr int kWsOut = 2;      // (cross dual, self dual) / blur^2 per cluster
+
+// Strided GEMM with a fused epilogue, see warmstart.hip.
+struct GemmArgs {
+    const float *A;
+    int64_t a_m, a_k;
+    const float *B;
+    int64_t b_k, b_n;
+    float *C;
+    int64_t ldc;
+    int M, N, K;
+    const float *bias;   // [N] or NULL
+    const float *G;      // group term rows (stride ldg) or NULL
+    int64_t ldg;
+    const int *grp;      // group of each output row (divided by grp_div)
+    int grp_div;
+    const float *rs;     // per-row scale of the group term or NULL
+    const float *mask;   // zero the output where mask <= 0 (stride ldm) or NULL
+    int64_t ldm;
+    int relu;
+};
+hipError_t launch_gemm(const GemmArgs &g, bool bf16, hipStream_t s);
+size_t colsum_part_len(int N);
+hipError_t launch_colsum(const float *A, int M, int N, int64_t ld, float *part, float *out,
+                         hipStream_t s);
+hipError_t launch_segsum(const float *X, const int *off, int stride, int n_seg, const float *w,
+                         int normalise, float *out, double *wsum, hipStream_t s);
+hipError_t launch_token_index(const int *off, int n_seg, const float *w, const double *wsum, int T,
+                              int *seg, float *share, float *lw, hipStream_t s);
+hipError_t launch_head(const float *a4, const float *W5, const float *b5, int T, const float *target,
+                       const float *lw, float *y, float *dy, double *tl, hipStream_t s);
+hipError_t launch_head_bwd(const float *dy, const float *W5, const float *a4, int T, float *da4,
+                           hipStream_t s);
+hipError_t launch_sum_f64(const double *v, int n, double *out, hipStream_t s);
+hipError_t launch_adam(int64_t n, float *theta, const float *grad, float *m, float *v, double lr,
+                       double b1, double b2, int step, double eps, hipStream_t s);
+hipError_t launch_tokens(const float *C, const float *cm, const float *rad, int k, int kp, int d,
+                         double total, double scale, int side, float *tok, float *tw, hipStream_t s);
+hipError_t launch_cluster_means(const int *perm, const int *off, const float *w, const float *p0,
+                                const float *p1, int k, double scale, float *out, hipStream_t s);
+hipError_t launch_expand(const int *lab, int64_t n, const float *pred, int k, double scale, float *p0,
+                         float *p1, int *bad, hipStream_t s);
+hipError_t launch_labels_from_perm(const int *perm, const int *off, int k, int *lab, hipStream_t s);
+hipError_t launch_nonfinite(const float *v, int64_t n, int *bad, hipStream_t s);
+hipError_t launch_check_labels(const int *lab, int n, int k, int *bad, hipStream_t s);
+// Stable counting sort of the labels in ws[0, n) (K-means workspace layout).
+hipError_t sort_labels(int n, int k, int *ws, int **perm_out, int **off_out, hipStream_t s);
+
 }  // namespace skh

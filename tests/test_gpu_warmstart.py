@@ -1,0 +1,290 @@
+"""GPU tests of the learned warm start.
+
+* Network forward (FP32 and BF16 inference) and the loss gradient of the
+  hand-written kernels against the FP64 network reference (whose backward pass
+  is pinned to finite differences on the CPU), Adam against its reference.
+* Tokens, cluster-mean targets and the broadcast against plain numpy
+  recomputations from the returned labels.
+* The solver: a start at the converged duals stops at the first check with the
+  same S; any start (even an untrained network's) reaches the cold fixed point
+  within the stopping tolerance; a non-finite start falls back to the cold run
+  bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import cuda, host, note
+from oracle import network as netref
+
+pytestmark = pytest.mark.gpu
+
+
+def _tokens(seg, seed):
+    rng = np.random.default_rng(seed)
+    T = seg[-1]
+    X = rng.standard_normal((T, 64)).astype(np.float32)
+    X[:, 62:] = 0.0
+    for s in range(len(seg) - 1):
+        X[seg[s]:seg[s + 1], 62 + (s % 2)] = 1.0
+    w = rng.uniform(0.05, 1.0, T).astype(np.float32)
+    tgt = rng.standard_normal((T, 2)).astype(np.float32)
+    return X, w, tgt
+
+
+def _ref_forward(theta, X, w, seg):
+    out = []
+    for p in range((len(seg) - 1) // 2):
+        b, mid, e = seg[2 * p], seg[2 * p + 1], seg[2 * p + 2]
+        out.append(netref.forward(theta, X[b:e], w[b:e], mid - b))
+    return np.concatenate(out)
+
+
+def _ref_loss_grad(theta, X, w, seg, tgt):
+    P = (len(seg) - 1) // 2
+    L, G = 0.0, np.zeros(netref.n_params())
+    for p in range(P):
+        b, mid, e = seg[2 * p], seg[2 * p + 1], seg[2 * p + 2]
+        l, g = netref.loss_and_grad(theta, X[b:e], w[b:e], mid - b, tgt[b:e])
+        L += l / P
+        G += g / P
+    return L, G
+
+
+def _net(theta):
+    import torch
+    from paper_2107_02010_amd.warm_start import WarmStartNet
+    return WarmStartNet("cuda", theta=torch.as_tensor(theta, dtype=torch.float32))
+
+
+SEGS = [[0, 37, 100], [0, 1, 2], [0, 70, 131, 200, 333, 334, 400]]
+
+
+@pytest.mark.parametrize("seg", SEGS)
+def test_forward_fp32_matches_reference(seg):
+    from paper_2107_02010_amd.warm_start import TokenBatch
+    X, w, _ = _tokens(seg, 1)
+    theta = (netref.init_params(2) * 0.8).astype(np.float32).astype(np.float64)
+    note(f"ws forward fp32 seg={seg}")
+    net = _net(theta)
+    y = host(net.forward(TokenBatch(cuda(X), cuda(w), seg), "fp32"))
+    r = _ref_forward(theta, X.astype(np.float64), w.astype(np.float64), seg)
+    scale = np.abs(r).max()
+    assert np.max(np.abs(y - r)) <= 2e-5 * scale + 1e-6, np.max(np.abs(y - r)) / scale
+
+
+def test_forward_bf16_inference_within_bf16_bound():
+    from paper_2107_02010_amd.warm_start import TokenBatch
+    seg = SEGS[2]
+    X, w, _ = _tokens(seg, 3)
+    theta = netref.init_params(4).astype(np.float32).astype(np.float64)
+    note("ws forward bf16")
+    net = _net(theta)
+    y = host(net.forward(TokenBatch(cuda(X), cuda(w), seg), "bf16x3"))
+    r = _ref_forward(theta, X.astype(np.float64), w.astype(np.float64), seg)
+    # bf16 operands (8-bit significand) through five layers: a few 2^-9 per layer
+    err = np.max(np.abs(y - r)) / np.abs(r).max()
+    assert err <= 3e-2, err
+
+
+@pytest.mark.parametrize("seg", [SEGS[0], SEGS[2]])
+def test_loss_gradient_matches_reference(seg):
+    from paper_2107_02010_amd.warm_start import TokenBatch
+    X, w, tgt = _tokens(seg, 5)
+    theta = (netref.init_params(6) * 0.8).astype(np.float32).astype(np.float64)
+    note(f"ws loss_grad seg={seg}")
+    net = _net(theta)
+    loss, g = net.loss_grad(TokenBatch(cuda(X), cuda(w), seg, cuda(tgt)))
+    g = host(g)
+    L, G = _ref_loss_grad(theta, X.astype(np.float64), w.astype(np.float64), seg,
+                          tgt.astype(np.float64))
+    assert loss == pytest.approx(L, rel=1e-5)
+    assert np.linalg.norm(g - G) <= 1e-4 * np.linalg.norm(G)
+    # every parameter block on its own (a mistake in one small block would hide in the total)
+    o = 0
+    for name, shape in netref.SHAPES:
+        k = int(np.prod(shape))
+        gb, Gb = g[o:o + k], G[o:o + k]
+        assert np.linalg.norm(gb - Gb) <= 1e-4 * np.linalg.norm(Gb) + 1e-9, name
+        o += k
+
+
+def test_adam_matches_reference():
+    import torch
+    rng = np.random.default_rng(7)
+    n = netref.n_params()
+    theta = rng.standard_normal(n).astype(np.float32)
+    net = _net(theta.astype(np.float64))
+    m = rng.standard_normal(n).astype(np.float32) * 0.1
+    v = rng.uniform(0, 0.1, n).astype(np.float32)
+    grad = rng.standard_normal(n).astype(np.float32)
+    net.m.copy_(torch.as_tensor(m))
+    net.v.copy_(torch.as_tensor(v))
+    net.step = 4  # the update below is step 5
+    note("ws adam")
+    net.adam(cuda(grad), lr=1e-3)
+    # the kernel takes its hyper-parameters in FP32: give the reference the same values
+    f32 = lambda t: float(np.float32(t))
+    t_ref, m_ref, v_ref = netref.adam_step(theta.astype(np.float64), grad.astype(np.float64),
+                                           m.astype(np.float64), v.astype(np.float64), 5,
+                                           f32(1e-3), beta1=f32(0.9), beta2=f32(0.999))
+    # FP32 rounding of b1 m + (1 - b1) g (and of v): a few units of the larger term
+    u = 2.0 ** -24
+    m64, v64, g64 = m.astype(np.float64), v.astype(np.float64), grad.astype(np.float64)
+    assert np.all(np.abs(host(net.m) - m_ref) <= 4 * u * (0.9 * np.abs(m64) + 0.1 * np.abs(g64)))
+    assert np.all(np.abs(host(net.v) - v_ref) <= 4 * u * (0.999 * v64 + 0.001 * g64 ** 2))
+    # the step lr m^ / (sqrt(v^) + eps): a few FP32 units of itself, the rounding of the
+    # new moment m (which may cancel) carried through, and the rounding of theta
+    step = np.abs(t_ref - theta.astype(np.float64))
+    c1, c2 = 1 - f32(0.9) ** 5, 1 - f32(0.999) ** 5
+    dm = 4 * u * (0.9 * np.abs(m64) + 0.1 * np.abs(g64))
+    carry = f32(1e-3) * dm / c1 / np.sqrt(v_ref / c2)
+    assert np.all(np.abs(host(net.theta) - t_ref) <= 16 * u * step + carry + 2 * u * np.abs(t_ref))
+
+
+def test_training_reduces_loss():
+    from paper_2107_02010_amd.warm_start import TokenBatch, WarmStartNet
+    rng = np.random.default_rng(8)
+    seg = [0, 150, 300, 420, 600]
+    T = seg[-1]
+    X = rng.uniform(-0.5, 0.5, (T, 64)).astype(np.float32)
+    w = rng.uniform(0.2, 1.0, T).astype(np.float32)
+    # a smooth target of the token and of its cloud's context
+    ctx = np.concatenate([np.repeat(X[seg[s]:seg[s + 1], 0].mean(), seg[s + 1] - seg[s])
+                          for s in range(4)])
+    tgt = np.stack([X[:, 0] * 3 + X[:, 1] ** 2, np.sin(3 * X[:, 2]) + ctx], 1).astype(np.float32)
+    batch = TokenBatch(cuda(X), cuda(w), seg, cuda(tgt))
+    net = WarmStartNet("cuda", seed=9)
+    note("ws training")
+    first = net.train_step(batch, 1e-3)
+    for _ in range(300):
+        last = net.train_step(batch, 1e-3)
+    assert last < 0.05 * first, (first, last)
+
+
+def _np_tokens(x, a, y, b, lx, ly, kx, ky):
+    lo = np.minimum(x.min(0), y.min(0)).astype(np.float64)
+    hi = np.maximum(x.max(0), y.max(0)).astype(np.float64)
+    mu = (0.5 * (lo + hi)).astype(np.float32).astype(np.float64)
+    diam = np.linalg.norm(hi - lo)
+    out = []
+    for pts, w, lab, k, side in ((x, a, lx, kx, 0), (y, b, ly, ky, 1)):
+        pts = pts.astype(np.float64) - mu
+        w = w.astype(np.float64)
+        M = w.sum()
+        T = np.zeros((k, 64))
+        tw = np.zeros(k)
+        for c in range(k):
+            sel = lab == c
+            mc = w[sel].sum()
+            cen = (w[sel, None] * pts[sel]).sum(0) / mc
+            T[c, :pts.shape[1]] = cen / diam
+            T[c, 60] = math.log(k * mc / M)
+            T[c, 61] = np.sqrt(((pts[sel] - cen) ** 2).sum(1).max()) / diam
+            T[c, 62 + side] = 1.0
+            tw[c] = mc
+        out.append((T, tw))
+    return np.concatenate([out[0][0], out[1][0]]), np.concatenate([out[0][1], out[1][1]])
+
+
+def test_tokens_targets_and_expand():
+    from paper_2107_02010_amd.warm_start import cluster_targets, cluster_tokens, expand
+    x, y = synth.blobs(3000, 11, d=5), synth.blobs(2500, 12, d=5)
+    a = synth.random_weights(3000, 13)
+    b = synth.random_weights(2500, 14, total=1.4)
+    note("ws tokens n=3000 m=2500 d=5")
+    tk = cluster_tokens(cuda(x), cuda(a), cuda(y), cuda(b), n_clusters=40, kmeans_iters=6)
+    kx, ky = tk["kx"], tk["ky"]
+    assert (kx, ky) == (40, 40)
+    lx = tk["labels_x"].cpu().numpy()
+    ly = tk["labels_y"].cpu().numpy()
+    assert lx.min() >= 0 and lx.max() < kx and ly.min() >= 0 and ly.max() < ky
+    T_ref, w_ref = _np_tokens(x, a, y, b, lx, ly, kx, ky)
+    T = host(tk["tokens"])
+    np.testing.assert_allclose(T, T_ref, rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(host(tk["w"]), w_ref, rtol=1e-6)
+    # targets: weighted cluster means of two potentials, scaled
+    rng = np.random.default_rng(15)
+    pc = rng.standard_normal(3000).astype(np.float32)
+    ps = rng.standard_normal(3000).astype(np.float32)
+    out = host(cluster_targets(tk["labels_x"], kx, cuda(a), cuda(pc), cuda(ps), 2.5))
+    for c in range(kx):
+        sel = lx == c
+        wc = a[sel].astype(np.float64)
+        assert out[c, 0] == pytest.approx(2.5 * (wc * pc[sel]).sum() / wc.sum(), rel=1e-6)
+        assert out[c, 1] == pytest.approx(2.5 * (wc * ps[sel]).sum() / wc.sum(), rel=1e-6)
+    # broadcast
+    pred = rng.standard_normal((kx, 2)).astype(np.float32)
+    f, p = expand(tk["labels_x"], kx, cuda(pred), 0.25)
+    np.testing.assert_array_equal(host(f), (0.25 * pred[lx, 0].astype(np.float64)).astype(np.float32))
+    np.testing.assert_array_equal(host(p), (0.25 * pred[lx, 1].astype(np.float64)).astype(np.float32))
+
+
+def test_targets_reject_bad_labels():
+    import torch
+    from paper_2107_02010_amd import SkhError
+    from paper_2107_02010_amd.warm_start import cluster_targets
+    lab = torch.tensor([0, 1, 5], dtype=torch.int32, device="cuda")
+    v = torch.ones(3, device="cuda")
+    with pytest.raises(SkhError):
+        cluster_targets(lab, 3, v, v, v, 1.0)
+
+
+def _blob_case():
+    x, a, y, b = synth.blob_pair(3000, seed=21)
+    return cuda(x), cuda(a), cuda(y), cuda(b)
+
+
+KW = dict(blur=0.05, reach=0.5, scaling=0.7, tol=1e-5, check_every=5, max_iters=4000)
+
+
+def test_start_at_converged_duals_stops_at_first_check():
+    import paper_2107_02010_amd as skh
+    x, a, y, b = _blob_case()
+    note("ws solver: start at converged duals")
+    S0, pot, st0 = skh.sinkhorn_divergence(x, a, y, b, potentials=True, **KW)
+    assert st0["converged"]
+    init = (pot["f"], pot["g"], pot["p"], pot["q"])
+    S1, _, st1 = skh.sinkhorn_divergence(x, a, y, b, potentials=True, init=init,
+                                         start_scale=KW["blur"], checked_init=True, **KW)
+    assert st1["converged"] and st1["warm_fallback"] == 0
+    assert st1["iters"] <= KW["check_every"] + 1 < st0["iters"]
+    assert S1 == pytest.approx(S0, rel=1e-5)
+
+
+def test_any_start_reaches_the_cold_fixed_point():
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd.warm_start import WarmStartNet, sinkhorn_divergence_warm
+    x, a, y, b = _blob_case()
+    note("ws solver: untrained network start")
+    S0, pot0, st0 = skh.sinkhorn_divergence(x, a, y, b, potentials=True, **KW)
+    net = WarmStartNet("cuda", seed=3)
+    kw = dict(KW)
+    blur = kw.pop("blur")
+    S1, pot1, st1 = sinkhorn_divergence_warm(net, x, a, y, b, blur, start_steps=6, **kw)
+    assert st0["converged"] and st1["converged"] and st1["warm_fallback"] == 0
+    assert S1 == pytest.approx(S0, rel=1e-4)
+    # unbalanced: the duals are unique; both runs stop within the marginal tolerance
+    rho = KW["reach"] ** 2
+    for k in ("f", "g", "p", "q"):
+        assert np.max(np.abs(host(pot1[k]) - host(pot0[k]))) <= 4 * rho * KW["tol"] + 1e-4
+
+
+def test_nonfinite_start_falls_back_to_cold():
+    import torch
+    import paper_2107_02010_amd as skh
+    x, a, y, b = _blob_case()
+    note("ws solver: NaN start fallback")
+    S0, pot0, st0 = skh.sinkhorn_divergence(x, a, y, b, potentials=True, **KW)
+    f = torch.zeros(x.shape[0], device="cuda")
+    f[17] = float("nan")
+    z = torch.zeros(y.shape[0], device="cuda")
+    S1, pot1, st1 = skh.sinkhorn_divergence(x, a, y, b, potentials=True,
+                                            init=(f, z, torch.zeros_like(f), z.clone()),
+                                            start_scale=KW["blur"], checked_init=True, **KW)
+    assert st1["warm_fallback"] == 1
+    assert S1 == S0 and st1["iters"] == st0["iters"]
+    for k in ("f", "g", "p", "q"):
+        assert torch.equal(pot0[k], pot1[k])
