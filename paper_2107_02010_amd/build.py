@@ -38,21 +38,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libskh)")
 
 
-def build(verbose: bool = False) -> str:
+def _compile(cc: str, src: str, obj: str, verbose: bool) -> None:
+    cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source (in parallel) and links libskh.so in place."""
+    from concurrent.futures import ThreadPoolExecutor
     cc = hipcc()
     tmpdir = tempfile.mkdtemp(prefix="skh_build_")
     try:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmpdir, src + ".o")
-            cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c",
-                   os.path.join(CSRC, src), "-o", obj]
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-            objs.append(obj)
+        objs = [os.path.join(tmpdir, src + ".o") for src in SOURCES]
+        workers = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(_compile, cc, src, obj, verbose) for src, obj in zip(SOURCES, objs)]:
+                f.result()
         tmp_lib = LIB + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
