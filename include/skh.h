@@ -51,6 +51,15 @@ enum {
  * in both modes. */
 enum { SKH_FP32 = 0, SKH_BF16_SPLIT = 1 };
 
+/* skh_params.fixed: the Algorithm's four updates form three independent loops
+ * (alpha<->alpha reads only p, beta<->beta only q, the cross pair only f and g;
+ * they meet in eq. (6) and the marginal check), so a loop whose fixed point is
+ * already known can be left out: its vectors are read from the caller's
+ * buffers (whatever init says), never updated, and its problems drop out of
+ * the launches and of the marginal check.  With the same scale list the other
+ * vectors come out exactly as in the full solve.  Dense solves only. */
+enum { SKH_FIX_P = 1, SKH_FIX_Q = 2, SKH_FIX_CROSS = 4 };
+
 /* skh_params.init: where the dual vectors start. */
 enum {
     SKH_INIT_COLD = 0,  /* zero, at the largest scale (the Algorithm's start) */
@@ -85,7 +94,8 @@ typedef struct skh_params {
     int32_t multiscale;  /* nonzero: K-means coarse phase + cluster-block truncation */
     int32_t n_clusters;  /* multiscale / split path: clusters per cloud; 0: ceil(sqrt(n)) */
     int32_t kmeans_iters;/* Lloyd iterations (>= 0) */
-    int32_t reserved[5]; /* must be zero */
+    int32_t fixed;       /* SKH_FIX_* bits: dual vectors that are inputs, kept as given */
+    int32_t reserved[4]; /* must be zero */
 } skh_params;
 
 /* Run statistics. */
@@ -112,7 +122,7 @@ typedef struct skh_stats {
  * diameter = 0 (auto), tol = 0 (schedule mode), extra_iters = 0,
  * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0,
  * multiscale = 0, jump_scale = 0, trunc_theta = 20, start_scale = 0,
- * n_clusters = 0, kmeans_iters = 10. */
+ * n_clusters = 0, kmeans_iters = 10, fixed = 0. */
 void skh_params_default(skh_params *p);
 
 /* Creates a context on HIP device `device` bound to stream `hip_stream`
@@ -155,6 +165,25 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
                             const float *y, const float *b, int64_t m, int32_t d,
                             const skh_params *params, double *S_out, float *f, float *g, float *p,
                             float *q, skh_stats *stats);
+
+/*
+ * The largest scale of the Algorithm's list for the pair (x, y): the diagonal
+ * of their joint bounding box (an upper bound of max |x_i - y_j|, the
+ * diameter of the parameter lines).  *out is a host double.  Synchronises.
+ */
+int skh_diameter(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
+                 double *out);
+
+/*
+ * Self dual vector p = a^{alpha<->alpha} alone: the Algorithm's alpha<->alpha
+ * loop (one softmin per iteration) with the scale list, damping and stopping
+ * rule of params (params->diameter should be the diameter of the full
+ * problem, so that p matches the p of that solve; <= 0: the diagonal of x's
+ * own bounding box).  init/start_scale apply to p; fixed must be 0.  p (n,
+ * device) is written; stats as for skh_sinkhorn_divergence (nullable).
+ */
+int skh_self_potential(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d,
+                       const skh_params *params, float *p, skh_stats *stats);
 
 /*
  * Transport plan of eq. (4) applied to column values:

@@ -231,10 +231,12 @@ def sinkhorn_divergence(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, ex
     return S, r
 
 
-def barycenter_steps(x, a, maps, steps, blur, reach=None, scaling=0.9, lr=1.0, extra_iters=0):
+def barycenter_steps(x, a, maps, steps, blur, reach=None, scaling=0.9, lr=1.0, extra_iters=0,
+                     diam=None):
     """Gradient descent on the support of alpha for (1/K) sum_k S(alpha, beta_k)
     (Section 3, track density atlas): x <- x - lr * mean_k grad_x S(alpha, beta_k) / a,
-    each S and gradient from the loop's dual vectors.  Returns (x, mean S per step)."""
+    each S and gradient from the loop's dual vectors (full solve per map; diam: the
+    largest scale of every solve, None: each pair's own).  Returns (x, mean S per step)."""
     x = _pts(x).copy()
     a = _f64(a)
     hist = []
@@ -242,7 +244,7 @@ def barycenter_steps(x, a, maps, steps, blur, reach=None, scaling=0.9, lr=1.0, e
         grad = np.zeros_like(x)
         tot = 0.0
         for y, b in maps:
-            S, r = sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling,
+            S, r = sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling, diam=diam,
                                        extra_iters=extra_iters)
             grad += grad_x(x, a, y, b, r["f"], r["g"], r["p"], float(blur) ** 2)
             tot += S

@@ -16,9 +16,10 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT  # noqa: F401
+from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT, SKH_FIX_P, SKH_FIX_Q, SKH_FIX_CROSS  # noqa: F401
 
-__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x",
+__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "diameter",
+           "self_potential",
            "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -95,14 +96,15 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
                         init=None, potentials: bool = False, timing: bool = False,
                         multiscale: bool = False, jump_scale: float = 0.0,
                         trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10,
-                        start_scale: float = 0.0, checked_init: bool = False):
+                        start_scale: float = 0.0, checked_init: bool = False, fixed: int = 0):
     """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
 
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
     tol > 0 selects converged mode (iterate at blur until the marginal error <= tol).
     init: optional (f, g, p, q) starting potentials; the schedule then starts at start_scale
     (<= 0: the diameter rule).  checked_init=True: non-finite starting values are discarded
-    and the call runs cold (stats["warm_fallback"] = 1).  With potentials=True returns
+    and the call runs cold (stats["warm_fallback"] = 1).  fixed: SKH_FIX_* bits of the loops
+    whose vectors are inputs (taken from init) and stay as given.  With potentials=True returns
     (S, dict(f=..., g=..., p=..., q=...), stats dict), else S (a Python float).
     timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
     multiscale=True: K-means coarse phase while sigma > jump_scale (0: RMS cluster radius,
@@ -130,6 +132,9 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     P.trunc_theta = float(trunc_theta)
     P.n_clusters = int(n_clusters)
     P.kmeans_iters = int(kmeans_iters)
+    P.fixed = int(fixed)
+    if fixed and init is None:
+        raise ValueError("fixed dual vectors are passed through init=(f, g, p, q)")
     dev = x.device
     if init is not None:
         f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in
@@ -151,6 +156,52 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     if potentials:
         return S.value, dict(f=f, g=g, p=p, q=q), st.as_dict()
     return S.value
+
+
+def diameter(x, y) -> float:
+    """Largest scale of the Algorithm's list for (x, y): the joint bounding-box diagonal."""
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    out = ctypes.c_double()
+    ctx = _Ctx.get(x.device)
+    rc = _lib.load().skh_diameter(ctx, _ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1],
+                                  ctypes.byref(out))
+    _lib.check(rc, ctx)
+    return out.value
+
+
+def self_potential(x, a, blur: float = 0.05, reach=None, scaling: float = 0.9, diameter=None,
+                   extra_iters: int = 0, tol: float = 0.0, max_iters: int = 1000,
+                   check_every: int = 5, precision: str = "fp32", init=None,
+                   start_scale: float = 0.0):
+    """The self dual vector p = a^{alpha<->alpha} of the Algorithm's alpha<->alpha loop alone.
+
+    With the diameter of a full problem (alpha, beta) it equals that solve's p.
+    Returns (p, stats dict)."""
+    x = _as_points(x, "x")
+    n, d = x.shape
+    a = _as_vec(a, n, "a", x.device)
+    P = _lib.default_params()
+    P.blur = float(blur)
+    P.reach = math.inf if reach is None else float(reach)
+    P.scaling = float(scaling)
+    P.diameter = 0.0 if diameter is None else float(diameter)
+    P.tol = float(tol)
+    P.extra_iters = int(extra_iters)
+    P.max_iters = int(max_iters)
+    P.check_every = int(check_every)
+    P.precision = _PREC[precision]
+    if init is not None:
+        p = _as_vec(init, n, "init", x.device).clone()
+        P.init = _lib.SKH_INIT_GIVEN
+        P.start_scale = float(start_scale)
+    else:
+        p = torch.empty(n, dtype=torch.float32, device=x.device)
+    st = _lib.SkhStats()
+    ctx = _Ctx.get(x.device)
+    rc = _lib.load().skh_self_potential(ctx, _ptr(x), _ptr(a), n, d, ctypes.byref(P), _ptr(p),
+                                        ctypes.byref(st))
+    _lib.check(rc, ctx, allow_not_converged=True)
+    return p, st.as_dict()
 
 
 def kmeans(x, w=None, k: int = None, iters: int = 10) -> dict:

@@ -22,6 +22,9 @@ SKH_ENONFINITE = -4
 SKH_FP32 = 0
 SKH_BF16_SPLIT = 1
 SKH_MAX_DIM = 63
+SKH_FIX_P = 1
+SKH_FIX_Q = 2
+SKH_FIX_CROSS = 4
 SKH_INIT_COLD = 0
 SKH_INIT_GIVEN = 1
 SKH_INIT_WARM = 2
@@ -40,7 +43,8 @@ class SkhParams(ctypes.Structure):
         ("jump_scale", _c_d), ("trunc_theta", _c_d), ("start_scale", _c_d),
         ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
         ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("multiscale", _c_i32),
-        ("n_clusters", _c_i32), ("kmeans_iters", _c_i32), ("reserved", _c_i32 * 5),
+        ("n_clusters", _c_i32), ("kmeans_iters", _c_i32), ("fixed", _c_i32),
+        ("reserved", _c_i32 * 4),
     ]
 
 
@@ -81,6 +85,9 @@ SIGNATURES = {
                             _c_vp, _c_d, _c_vp]),
     "skh_kmeans": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp,
                             _c_vp, _c_vp, _c_vp]),
+    "skh_diameter": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, ctypes.POINTER(_c_d)]),
+    "skh_self_potential": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_i32, ctypes.POINTER(SkhParams),
+                                    _c_vp, ctypes.POINTER(SkhStats)]),
     "skh_ws_tokens": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_i32,
                                _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp,
                                ctypes.POINTER(_c_i32)]),

@@ -2,46 +2,85 @@
 support points (Section 3, "Track density atlas").
 
 The loss is (1/K) sum_k S_{eps,rho}(alpha, beta_k) over the positions x_i of
-alpha = sum_i a_i delta_{x_i}; each step solves the K divergences on the GPU,
-takes the x-gradient of each from its dual vectors (hand-written kernel), and
-moves every point by x_i <- x_i - lr * grad_i / a_i.  With p = 2, reach = inf
-and blur = one voxel this is the paper's probabilistic atlas.
+alpha = sum_i a_i delta_{x_i}; each step moves every point by
+x_i <- x_i - lr * mean_k grad_x S(alpha, beta_k) / a_i.
+
+The Algorithm's four updates form three independent loops (alpha<->alpha reads
+only p, beta<->beta only q, the cross pair only f and g), so with one scale
+list for all maps a step needs:
+  * the self vector p of alpha once (it does not depend on the map),
+  * the self vectors q_k of the maps once for the whole descent (the maps do
+    not move),
+  * per map only the cross loop (two softmins per iteration), with p and q_k
+    fixed,
+and gives the same S_k, f_k, g_k as K full solves with that scale list.  The
+common largest scale is the largest joint bounding-box diagonal over the maps
+at the start (any upper bound of the distances is a valid first scale).
 """
 from __future__ import annotations
 
 import torch
 
-from . import grad_x, sinkhorn_divergence
+from . import SKH_FIX_P, SKH_FIX_Q, diameter, grad_x, self_potential, sinkhorn_divergence
+
+
+class Barycenter:
+    """Gradient descent on the support of alpha against K fixed maps."""
+
+    def __init__(self, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
+                 lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0, x0=None):
+        self.a = a
+        self.maps = maps
+        self.kw = dict(blur=blur, reach=reach, scaling=scaling, precision=precision,
+                       extra_iters=extra_iters)
+        self.lr = lr
+        self.d = None if x0 is None else max(diameter(x0, y) for y, _ in maps)
+        self.q = None
+
+    def _setup(self, x):
+        if self.d is None:
+            self.d = max(diameter(x, y) for y, _ in self.maps)
+        if self.q is None:
+            self.q = [self_potential(y, b, diameter=self.d, **self.kw)[0] for y, b in self.maps]
+
+    def step(self, x):
+        """One descent step; returns (new x, mean S, per-map potential dicts)."""
+        self._setup(x)
+        p, _ = self_potential(x, self.a, diameter=self.d, **self.kw)
+        grad = torch.zeros_like(x)
+        total = 0.0
+        pots = []
+        for (y, b), q in zip(self.maps, self.q):
+            zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
+            zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
+            S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d, init=(zf, zg, p, q),
+                                            fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
+                                            **self.kw)
+            grad += grad_x(x, self.a, y, b, pot["f"], pot["g"], pot["p"], self.kw["blur"])
+            total += S
+            pots.append(pot)
+        grad /= len(self.maps)
+        return x - self.lr * grad / self.a[:, None], total / len(self.maps), pots
 
 
 def barycenter_step(x, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
                     lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0,
-                    init=None):
-    """One gradient step.  maps: list of (y_k, b_k) CUDA tensors.
+                    diameter_=None):
+    """One gradient step with the scale list from diameter_ (None: the largest joint
+    bounding-box diagonal of x with each map).  maps: list of (y_k, b_k) CUDA tensors.
 
-    Returns (new x, mean S, list of per-map potentials dicts).
-    """
-    K = len(maps)
-    grad = torch.zeros_like(x)
-    total = 0.0
-    pots = []
-    for k, (y, b) in enumerate(maps):
-        kw = dict(blur=blur, reach=reach, scaling=scaling, precision=precision,
-                  extra_iters=extra_iters, potentials=True)
-        S, pot, _ = sinkhorn_divergence(x, a, y, b, **kw)
-        grad += grad_x(x, a, y, b, pot["f"], pot["g"], pot["p"], blur)
-        total += S
-        pots.append(pot)
-    grad /= K
-    x_new = x - lr * grad / a[:, None]
-    return x_new, total / K, pots
+    Returns (new x, mean S, list of per-map potentials dicts)."""
+    B = Barycenter(a, maps, blur, reach, scaling, lr, precision, extra_iters)
+    B.d = diameter_
+    return B.step(x)
 
 
 def wasserstein_barycenter(x0, a, maps, steps: int = 10, **kw):
     """Runs `steps` gradient steps from x0; returns (x, list of mean S per step)."""
+    B = Barycenter(a, maps, x0=x0, **kw)
     x = x0.clone()
     history = []
     for _ in range(steps):
-        x, S, _ = barycenter_step(x, a, maps, **kw)
+        x, S, _ = B.step(x)
         history.append(S)
     return x, history

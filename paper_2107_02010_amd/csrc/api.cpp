@@ -299,8 +299,16 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         return fail(ctx, SKH_EINVAL, "negative count parameter");
     if (P.precision != SKH_FP32 && P.precision != SKH_BF16_SPLIT)
         return fail(ctx, SKH_EINVAL, "unknown precision");
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 4; ++k)
         if (P.reserved[k]) return fail(ctx, SKH_EINVAL, "reserved params must be zero");
+    const int fixed = P.fixed;
+    if (fixed & ~(SKH_FIX_P | SKH_FIX_Q | SKH_FIX_CROSS))
+        return fail(ctx, SKH_EINVAL, "unknown fixed bits");
+    if (fixed && P.multiscale)
+        return fail(ctx, SKH_EINVAL, "fixed dual vectors need a dense solve");
+    if (((fixed & SKH_FIX_P) && !p) || ((fixed & SKH_FIX_Q) && !q) ||
+        ((fixed & SKH_FIX_CROSS) && (!f || !g)))
+        return fail(ctx, SKH_EINVAL, "fixed dual vectors must be given");
     if (P.init != SKH_INIT_COLD && P.init != SKH_INIT_GIVEN && P.init != SKH_INIT_WARM)
         return fail(ctx, SKH_EINVAL, "unknown init mode");
     if (std::isnan(P.start_scale)) return fail(ctx, SKH_EINVAL, "NaN parameter");
@@ -482,8 +490,11 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     // job 2: a~^{a->b} (rows y, cols x); job 3: b~^{b->a} (rows x, cols y).
     const int64_t nr[4] = {nn, mm, mm, nn}, nc[4] = {nn, mm, nn, mm};
     Clustered *rowc[4] = {&cx, &cy, &cy, &cx}, *colc[4] = {&cx, &cy, &cx, &cy};
+    // problems of a fixed loop get no rows: no workgroups, no updates
+    const bool skip_job[4] = {(fixed & SKH_FIX_P) != 0, (fixed & SKH_FIX_Q) != 0,
+                              (fixed & SKH_FIX_CROSS) != 0, (fixed & SKH_FIX_CROSS) != 0};
     for (int k = 0; k < 4; ++k) {
-        batch.job[k].n_rows = (int)nr[k];
+        batch.job[k].n_rows = skip_job[k] ? 0 : (int)nr[k];
         batch.job[k].n_cols = (int)nc[k];
         if (ms) {
             batch.job[k].n_tiles = rowc[k]->n_tiles;
@@ -560,24 +571,28 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         }
     }
     float *F = pot[0], *G = pot[1], *Pp = pot[2], *Q = pot[3];
-    if (P.init) {
-        if (clustered) {
-            SKH_HIP(skh::launch_permute(f, cx.perm_pad, cx.n_pad, F, s));
-            SKH_HIP(skh::launch_permute(p, cx.perm_pad, cx.n_pad, Pp, s));
-            SKH_HIP(skh::launch_permute(g, cy.perm_pad, cy.n_pad, G, s));
-            SKH_HIP(skh::launch_permute(q, cy.perm_pad, cy.n_pad, Q, s));
+    {
+        // given values (init, or a fixed loop) are read from the caller; the rest start at 0
+        const bool given[4] = {P.init || (fixed & SKH_FIX_CROSS), P.init || (fixed & SKH_FIX_CROSS),
+                               P.init || (fixed & SKH_FIX_P), P.init || (fixed & SKH_FIX_Q)};
+        const float *src[4] = {f, g, p, q};
+        const Clustered *cl[4] = {&cx, &cy, &cx, &cy};
+        for (int k = 0; k < 4; ++k) {
+            if (given[k]) {
+                if (clustered)
+                    SKH_HIP(skh::launch_permute(src[k], cl[k]->perm_pad, cl[k]->n_pad, pot[k], s));
+            } else {
+                SKH_HIP(hipMemsetAsync(pot[k], 0, plen[k] * sizeof(float), s));
+            }
         }
-    } else {
-        SKH_HIP(hipMemsetAsync(F, 0, nn * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(Pp, 0, nn * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(G, 0, mm * sizeof(float), s));
-        SKH_HIP(hipMemsetAsync(Q, 0, mm * sizeof(float), s));
     }
     if (ms) SKH_HIP(hipMemsetAsync(pairs_ctr, 0, sizeof(unsigned long long), s));
 
     // ---- Coarse phase: the loop on the K-means centres, then the jump ----
     double pairs = 0.0, dense_pairs = 0.0;
-    const double pairs_per_iter = (double)n * n + (double)m * m + 2.0 * (double)n * m;
+    const double pairs_per_iter = (skip_job[0] ? 0.0 : (double)n * n) +
+                                  (skip_job[1] ? 0.0 : (double)m * m) +
+                                  (skip_job[2] ? 0.0 : 2.0 * (double)n * m);
     if (ms && t_jump > 0) {
         float *Fc = cpot[0], *Gc = cpot[1], *Pc = cpot[2], *Qc = cpot[3];
         for (int k = 0; k < 4; ++k) SKH_HIP(hipMemsetAsync(cpot[k], 0, (k % 2 ? ky : kx) * sizeof(float), s));
@@ -691,8 +706,8 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         }
     }
     skh::FinishSide sx{}, sy{};
-    sx.part_self = part[0];
-    sx.part_cross = part[3];
+    sx.part_self = skip_job[0] ? nullptr : part[0];
+    sx.part_cross = skip_job[3] ? nullptr : part[3];
     sx.chunks_self = batch.job[0].n_chunks;
     sx.chunks_cross = batch.job[3].n_chunks;
     sx.n = nn;
@@ -703,8 +718,8 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     sx.pot_cross = F;
     sx.u_self = u[0];
     sx.u_cross = u[2];
-    sy.part_self = part[1];
-    sy.part_cross = part[2];
+    sy.part_self = skip_job[1] ? nullptr : part[1];
+    sy.part_cross = skip_job[2] ? nullptr : part[2];
     sy.chunks_self = batch.job[1].n_chunks;
     sy.chunks_cross = batch.job[2].n_chunks;
     sy.n = mm;
@@ -991,6 +1006,82 @@ int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const fl
     if (rc) return rc;
     SKH_HIP(skh::launch_grad_combine(Xp, (int)n, d, kp, P1, m1, P2, m2, grad, s));
     return SKH_OK;
+}
+
+int skh_diameter(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
+                 double *out) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !y || !out) return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
+        return fail(ctx, SKH_EINVAL, "n, m out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
+    float *plo, *phi, *lohi;
+    double *pmass, *mass;
+    int *pbad, *bad;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[0] : nullptr);
+        plo = c.take<float>((size_t)(nbx + nby) * 64);
+        phi = c.take<float>((size_t)(nbx + nby) * 64);
+        pmass = c.take<double>(nbx + nby);
+        pbad = c.take<int>(2 * (nbx + nby));
+        lohi = c.take<float>(192);
+        mass = c.take<double>(2);
+        bad = c.take<int>(4);
+        if (!pass) {
+            int rc = ensure_ws(ctx, 0, c.off);
+            if (rc) return rc;
+        }
+    }
+    SKH_HIP(skh::launch_bbox_partial(x, nullptr, n, d, plo, phi, pmass, pbad, s));
+    SKH_HIP(skh::launch_bbox_partial(y, nullptr, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
+                                     pmass + nbx, pbad + 2 * nbx, s));
+    SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nbx, nby, d, lohi, mass, bad, s));
+    char *hb = static_cast<char *>(ctx->host);
+    SKH_HIP(hipMemcpyAsync(hb, lohi, 128 * sizeof(float), hipMemcpyDeviceToHost, s));
+    SKH_HIP(hipMemcpyAsync(hb + 528, bad, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    SKH_HIP(hipStreamSynchronize(s));
+    const float *hlo = reinterpret_cast<const float *>(hb);
+    const int *hbad = reinterpret_cast<const int *>(hb + 528);
+    if (hbad[0] || hbad[2]) return fail(ctx, SKH_ENONFINITE, "non-finite coordinate");
+    double s2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double t = (double)hlo[64 + k] - (double)hlo[k];
+        s2 += t * t;
+    }
+    *out = std::sqrt(s2);
+    return SKH_OK;
+}
+
+int skh_self_potential(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d,
+                       const skh_params *params, float *p, skh_stats *stats) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !a || !params || !p) return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (n < 1 || n > kMaxPoints) return fail(ctx, SKH_EINVAL, "n out of range");
+    if (params->fixed) return fail(ctx, SKH_EINVAL, "fixed must be 0");
+    if (params->multiscale) return fail(ctx, SKH_EINVAL, "the self loop runs dense");
+    // the alpha<->alpha loop of the pair (alpha, alpha); the other three vectors
+    // are zero placeholders, fixed, in the network workspace
+    float *dummy;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[2] : nullptr);
+        dummy = c.take<float>((size_t)3 * n);
+        if (!pass) {
+            int rc = ensure_ws(ctx, 2, c.off);
+            if (rc) return rc;
+        }
+    }
+    {
+        DeviceGuard guard(ctx->device);
+        SKH_HIP(hipMemsetAsync(dummy, 0, (size_t)3 * n * sizeof(float), ctx->stream));
+    }
+    skh_params P2 = *params;
+    P2.fixed = SKH_FIX_Q | SKH_FIX_CROSS;
+    int rc = skh_sinkhorn_divergence(ctx, x, a, n, x, a, n, d, &P2, nullptr, dummy, dummy + n, p,
+                                     dummy + 2 * n, stats);
+    return rc;
 }
 
 int skh_kmeans(skh_ctx *ctx, const float *x, const float *w, int64_t n, int32_t d, int32_t k,

@@ -269,32 +269,42 @@ __global__ __launch_bounds__(kThreads) void k_iteration_finish(FinishSide sx, Fi
     const int64_t i = (int64_t)(is_x ? blockIdx.x : blockIdx.x - nbx) * kThreads + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < S.n) {
+        // a problem without partials belongs to a fixed loop: its vector is left as given
+        const bool has_s = S.part_self != nullptr, has_c = S.part_cross != nullptr;
         const double hn = S.hn[i];
-        const double L2s = merge_l2(S.part_self, S.chunks_self, S.n, i);
-        const double L2c = merge_l2(S.part_cross, S.chunks_cross, S.n, i);
+        const double L2s = has_s ? merge_l2(S.part_self, S.chunks_self, S.n, i) : 0.0;
+        const double L2c = has_c ? merge_l2(S.part_cross, S.chunks_cross, S.n, i) : 0.0;
         const double ts = lam * (hn - eps * kLn2 * L2s);
         const double tc = lam * (hn - eps * kLn2 * L2c);
         const double ps = S.pot_self[i], pc = S.pot_cross[i];
         if (check) {
             const double wi = S.w[i];
             if (wi > 0.0) {
-                const double rc = wi * exp((pc - hn) / eps + kLn2 * L2c);
-                const double rs = wi * exp((ps - hn) / eps + kLn2 * L2s);
-                const double tgc = balanced ? wi : wi * exp(-pc / rho);
-                const double tgs = balanced ? wi : wi * exp(-ps / rho);
-                v[0] = fabs(rc - tgc);
-                v[1] = tgc;
-                v[2] = fabs(rs - tgs);
-                v[3] = tgs;
+                if (has_c) {
+                    const double rc = wi * exp((pc - hn) / eps + kLn2 * L2c);
+                    const double tgc = balanced ? wi : wi * exp(-pc / rho);
+                    v[0] = fabs(rc - tgc);
+                    v[1] = tgc;
+                }
+                if (has_s) {
+                    const double rs = wi * exp((ps - hn) / eps + kLn2 * L2s);
+                    const double tgs = balanced ? wi : wi * exp(-ps / rho);
+                    v[2] = fabs(rs - tgs);
+                    v[3] = tgs;
+                }
             }
         }
-        const float ns = (float)(0.5 * (ps + ts));
-        const float nc = (float)(0.5 * (pc + tc));
-        S.pot_self[i] = ns;
-        S.pot_cross[i] = nc;
         const float lw = S.lw[i], hnf = S.hn[i];
-        S.u_self[i] = col_offset(lw, (double)ns, hnf, inv_eps_next);
-        S.u_cross[i] = col_offset(lw, (double)nc, hnf, inv_eps_next);
+        if (has_s) {
+            const float ns = (float)(0.5 * (ps + ts));
+            S.pot_self[i] = ns;
+            S.u_self[i] = col_offset(lw, (double)ns, hnf, inv_eps_next);
+        }
+        if (has_c) {
+            const float nc = (float)(0.5 * (pc + tc));
+            S.pot_cross[i] = nc;
+            S.u_cross[i] = col_offset(lw, (double)nc, hnf, inv_eps_next);
+        }
     }
     if (check) block_sum4(v, acc + (size_t)blockIdx.x * 4);
 }

@@ -17,6 +17,7 @@ from __future__ import annotations
 import ctypes
 import json
 import math
+import os
 
 import torch
 
@@ -24,6 +25,9 @@ from . import _lib
 from . import _Ctx, _as_points, _as_vec, _ptr, sinkhorn_divergence
 
 N_PARAMS = _lib.SKH_WS_N_PARAMS
+# network trained by ws_train on fibre pairs (blur 1 mm, reach 20 mm, scaling 0.9)
+DEFAULT_CHECKPOINT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                                  "ws_fibers.safetensors")
 WIDTH = _lib.SKH_WS_WIDTH
 IN = _lib.SKH_WS_IN
 _SHAPES = [(WIDTH, IN), (WIDTH,), (WIDTH, WIDTH), (WIDTH,), (WIDTH, WIDTH), (WIDTH,),

@@ -40,20 +40,32 @@ def solve_kw(args):
                 max_iters=args.max_iters, multiscale=True, precision=args.precision)
 
 
-def draw_pair(rng, args, seed):
-    n = int(round(math.exp(rng.uniform(math.log(args.n_min), math.log(args.n_max)))))
-    bundles = int(rng.integers(args.b_min, args.b_max + 1))
+def pair_plan(args, count, seed0):
+    """(n, bundles, seed) of each pair: N log-uniform, bundles uniform, fresh seeds."""
+    rng = np.random.default_rng(seed0)
+    plan = []
+    for i in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(args.n_min), math.log(args.n_max)))))
+        bundles = int(rng.integers(args.b_min, args.b_max + 1))
+        plan.append((n, bundles, seed0 * 1000 + 7 * i))
+    return plan
+
+
+def _make_pair(spec):
+    """Host-side generation of one pair (runs in a worker process, no GPU)."""
+    n, bundles, seed = spec
     x, a, y, b = synth.fiber_pair(n, bundles, seed)
+    return spec, x, a, y, b
+
+
+def generate(args, pool, count, seed0, label):
+    out = []
     dev = torch.device("cuda")
     t = lambda v: torch.as_tensor(v, dtype=torch.float32, device=dev)
-    return n, bundles, t(x), t(a), t(y), t(b)
-
-
-def generate(args, count, seed0, label):
-    rng = np.random.default_rng(seed0)
-    out = []
-    for i in range(count):
-        n, nb, x, a, y, b = draw_pair(rng, args, seed0 * 1000 + 7 * i)
+    plan = pair_plan(args, count, seed0)
+    pairs = pool.imap(_make_pair, plan) if pool is not None else map(_make_pair, plan)
+    for i, ((n, nb, seed), x, a, y, b) in enumerate(pairs):
+        x, a, y, b = t(x), t(a), t(y), t(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ex, S, st = make_example(x, a, y, b, blur=args.blur, **solve_kw(args))
@@ -61,7 +73,7 @@ def generate(args, count, seed0, label):
         dt = time.perf_counter() - t0
         ex = {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in ex.items()}
         ex.update(n=n, bundles=nb, S=S, iters=st["iters"], coarse=st["coarse_iters"],
-                  converged=st["converged"], seconds=dt, seed=seed0 * 1000 + 7 * i)
+                  converged=st["converged"], seconds=dt, seed=seed)
         out.append(ex)
         print(f"[{label} {i + 1}/{count}] n={n} bundles={nb} S={S:.6g} iters={st['iters']} "
               f"coarse={st['coarse_iters']} conv={st['converged']} {dt:.2f}s", flush=True)
@@ -91,16 +103,16 @@ def train(net, data, val, args):
 
 
 def pick_start_steps(net, val, args):
-    """Times warm solves of the validation pairs for each candidate s."""
+    """Times warm solves of the validation pairs for each candidate s (same stopping
+    rule as the cold solves that made the examples); reports the S difference."""
     best = None
     table = {}
+    dev = torch.device("cuda")
+    t = lambda v: torch.as_tensor(v, dtype=torch.float32, device=dev)
+    clouds = [tuple(t(v) for v in synth.fiber_pair(e["n"], e["bundles"], e["seed"])) for e in val]
     for s in args.start_candidates:
-        tot_t, tot_it = 0.0, 0
-        for e in val:
-            x, a, y, b = synth.fiber_pair(e["n"], e["bundles"], e["seed"])
-            dev = torch.device("cuda")
-            t = lambda v: torch.as_tensor(v, dtype=torch.float32, device=dev)
-            x, a, y, b = t(x), t(a), t(y), t(b)
+        tot_t, tot_it, dS = 0.0, 0, 0.0
+        for e, (x, a, y, b) in zip(val, clouds):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             S, _, st = sinkhorn_divergence_warm(net, x, a, y, b, args.blur, start_steps=s,
@@ -108,10 +120,11 @@ def pick_start_steps(net, val, args):
             torch.cuda.synchronize()
             tot_t += time.perf_counter() - t0
             tot_it += st["iters"]
+            dS = max(dS, abs(S - e["S"]) / abs(e["S"]))
         cold_t = sum(e["seconds"] for e in val)
-        table[s] = dict(seconds=tot_t, iters=tot_it)
+        table[s] = dict(seconds=tot_t, iters=tot_it, max_rel_dS=dS)
         print(f"[start] s={s} warm {tot_t:.2f}s {tot_it} iters (cold {cold_t:.2f}s "
-              f"{sum(e['iters'] for e in val)} iters)", flush=True)
+              f"{sum(e['iters'] for e in val)} iters), max |dS|/S = {dS:.2e}", flush=True)
         if best is None or tot_t < table[best]["seconds"]:
             best = s
     return best, table
@@ -138,18 +151,25 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=250)
     ap.add_argument("--start-candidates", type=int, nargs="+", default=[0, 2, 4, 8, 12])
     ap.add_argument("--data", default=None, help="cache of generated examples (.pt, tensors only)")
+    ap.add_argument("--workers", type=int, default=8, help="host processes generating pairs")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+    # the generator pool starts before this process touches the GPU
+    import multiprocessing as mp
+    pool = mp.get_context("spawn").Pool(args.workers) if args.workers > 1 else None
 
     if args.data and os.path.exists(args.data):
         blob = torch.load(args.data, weights_only=True)
         data, val = blob["train"], blob["val"]
         print(f"[data] loaded {len(data)} + {len(val)} examples from {args.data}", flush=True)
     else:
-        data = generate(args, args.pairs, args.seed + 100, "gen")
-        val = generate(args, args.val, args.seed + 200, "val")
+        data = generate(args, pool, args.pairs, args.seed + 100, "gen")
+        val = generate(args, pool, args.val, args.seed + 200, "val")
         if args.data:
             torch.save({"train": data, "val": val}, args.data)
+    if pool is not None:
+        pool.close()
+        pool.join()
     net = WarmStartNet("cuda", seed=args.seed)
     train(net, data, val, args)
     best, table = pick_start_steps(net, val, args)

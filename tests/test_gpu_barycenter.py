@@ -22,7 +22,12 @@ def test_barycenter_steps_match_oracle():
     note("barycenter 3 maps 24^3, 400 support, 2 steps")
     xg, hg = wasserstein_barycenter(cuda(x0), cuda(a), [(cuda(c), cuda(w)) for c, w in maps],
                                     steps=2, **kw)
-    xr, hr = oracle.barycenter_steps(x0, a, maps, 2, **kw)
+    # the oracle runs a full solve per map with the same largest scale: the largest joint
+    # bounding-box diagonal of the initial support with each map
+    diam = max(np.linalg.norm(np.maximum(x0.max(0), c.max(0)).astype(np.float64)
+                              - np.minimum(x0.min(0), c.min(0)).astype(np.float64))
+               for c, _ in maps)
+    xr, hr = oracle.barycenter_steps(x0, a, maps, 2, diam=diam, **kw)
     assert hg[0] == pytest.approx(hr[0], rel=1e-4)
     assert hg[1] == pytest.approx(hr[1], rel=1e-3)
     assert hg[1] < hg[0]  # the loss decreases
@@ -44,3 +49,54 @@ def test_barycenter_full_shape_one_step():
     ybar = np.mean([(w[:, None].astype(np.float64) * c).sum(0) for c, w in maps], axis=0)
     print("support mean after one step", g.astype(np.float64).mean(0), "target", ybar)
     np.testing.assert_allclose(g.astype(np.float64).mean(0), ybar, atol=0.5)
+
+
+def _pair(n, m, seed):
+    x, a, y, b = synth.blob_pair(n, seed=seed)
+    b = synth.random_weights(m, seed + 5, total=1.0) if m == n else b
+    return x, a, y, b
+
+
+@pytest.mark.parametrize("reach,precision", [(None, "fp32"), (0.4, "fp32"), (None, "bf16x3")])
+def test_fixed_self_loops_reproduce_the_full_solve(reach, precision):
+    """p and q from their own loops, then the cross loop alone with p, q fixed: the same
+    S, f, g as the full solve with the same scale list (the three loops are independent)."""
+    import torch
+    import paper_2107_02010_amd as skh
+    x, a, y, b = _pair(1500, 1500, 31)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    kw = dict(blur=0.02, reach=reach, scaling=0.7, precision=precision, extra_iters=3)
+    d = skh.diameter(X, Y)
+    note(f"fixed self loops reach={reach} {precision}")
+    S0, pot0, st0 = skh.sinkhorn_divergence(X, A, Y, B, diameter=d, potentials=True, **kw)
+    p, _ = skh.self_potential(X, A, diameter=d, **kw)
+    q, _ = skh.self_potential(Y, B, diameter=d, **kw)
+    tol = 1e-5 if precision == "fp32" else 1e-3
+    scale = max(kw["blur"] ** 2, float(torch.abs(pot0["f"]).max()))
+    assert torch.max(torch.abs(p - pot0["p"])).item() <= tol * scale
+    assert torch.max(torch.abs(q - pot0["q"])).item() <= tol * scale
+    z = lambda k: torch.zeros(k, device="cuda")
+    S1, pot1, st1 = skh.sinkhorn_divergence(X, A, Y, B, diameter=d, potentials=True,
+                                            init=(z(len(x)), z(len(y)), p, q),
+                                            fixed=skh.SKH_FIX_P | skh.SKH_FIX_Q, **kw)
+    assert st1["iters"] == st0["iters"]
+    assert st1["pairs"] == pytest.approx(2.0 * len(x) * len(y) * st1["iters"])
+    assert S1 == pytest.approx(S0, rel=tol)
+    for k in ("f", "g"):
+        assert torch.max(torch.abs(pot1[k] - pot0[k])).item() <= tol * scale
+    assert torch.equal(pot1["p"], p) and torch.equal(pot1["q"], q)  # fixed: returned as given
+
+
+def test_fixed_loops_argument_checks():
+    import torch
+    import paper_2107_02010_amd as skh
+    x, a, y, b = _pair(200, 200, 33)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    z = torch.zeros(200, device="cuda")
+    with pytest.raises(ValueError):
+        skh.sinkhorn_divergence(X, A, Y, B, fixed=skh.SKH_FIX_P)
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=8)
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=skh.SKH_FIX_P,
+                                multiscale=True)

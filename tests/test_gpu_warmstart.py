@@ -288,3 +288,32 @@ def test_nonfinite_start_falls_back_to_cold():
     assert S1 == S0 and st1["iters"] == st0["iters"]
     for k in ("f", "g", "p", "q"):
         assert torch.equal(pot0[k], pot1[k])
+
+
+def test_trained_network_gains_on_fresh_pairs():
+    """The committed network against the cold Algorithm on fibre pairs it never saw
+    (seeds outside the training range): same stopping rule, same fixed point, fewer
+    iterations."""
+    import os
+    import torch
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd.warm_start import DEFAULT_CHECKPOINT, WarmStartNet, sinkhorn_divergence_warm
+    if not os.path.exists(DEFAULT_CHECKPOINT):
+        pytest.skip("no trained warm-start network in the tree")
+    net = WarmStartNet.load(DEFAULT_CHECKPOINT, "cuda")
+    kw = dict(reach=20.0, scaling=0.9, tol=1e-4, check_every=5, max_iters=5000,
+              multiscale=True, precision="bf16x3")
+    cold_it = warm_it = 0
+    for n, bundles, seed in ((30000, 80, 9_000_001), (60000, 150, 9_000_011), (45000, 120, 9_000_021)):
+        x, a, y, b = synth.fiber_pair(n, bundles, seed)
+        x, a, y, b = cuda(x), cuda(a), cuda(y), cuda(b)
+        note(f"ws gain: fibres n={n} bundles={bundles} seed={seed}")
+        S0, pot0, st0 = skh.sinkhorn_divergence(x, a, y, b, blur=1.0, potentials=True, **kw)
+        S1, pot1, st1 = sinkhorn_divergence_warm(net, x, a, y, b, 1.0, **kw)
+        assert st0["converged"] and st1["converged"] and st1["warm_fallback"] == 0
+        assert S1 == pytest.approx(S0, rel=1e-4), (n, S0, S1)
+        for k in ("f", "g", "p", "q"):
+            assert torch.max(torch.abs(pot1[k] - pot0[k])).item() <= 4 * 400.0 * 1e-4 + 1e-3
+        cold_it += st0["iters"]
+        warm_it += st1["iters"]
+    assert warm_it < 0.5 * cold_it, (warm_it, cold_it)

@@ -446,3 +446,24 @@ def test_plan_apply_marginal_and_labels():
     lab = oracle.plan_apply(x, a, y, b, r["f"], r["g"], blur ** 2, labels, divide_by_a=True)
     assert np.all(lab >= 0)
     np.testing.assert_allclose(lab.sum(1), 1.0, rtol=1e-9)
+
+
+@pytest.mark.parametrize("reach", [None, 0.5])
+def test_self_and_cross_loops_are_independent(reach):
+    # In the Algorithm every update reads the previous values of one loop only:
+    # p~ from p (alpha<->alpha), q~ from q (beta<->beta), f~ from g and g~ from f.
+    # With the same scale list, the p of the pair (alpha, beta) is therefore the p of
+    # the pair (alpha, alpha), whatever beta is; the barycenter shares it over maps.
+    rng = np.random.default_rng(41)
+    x = rng.uniform(0, 1, (30, 2))
+    y = rng.uniform(0, 1, (25, 2)) + 0.3
+    y2 = rng.normal(0.5, 0.2, (40, 2))
+    a, b, b2 = _w(30, 1), _w(25, 2), _w(40, 3)
+    kw = dict(blur=0.05, reach=reach, scaling=0.7, diam=3.0, extra_iters=4)
+    _, r1 = oracle.sinkhorn_divergence(x, a, y, b, **kw)
+    _, r2 = oracle.sinkhorn_divergence(x, a, y2, b2, **kw)
+    _, r3 = oracle.sinkhorn_divergence(x, a, x, a, **kw)
+    np.testing.assert_array_equal(r1["p"], r2["p"])
+    np.testing.assert_array_equal(r1["p"], r3["p"])
+    _, r4 = oracle.sinkhorn_divergence(y, b, y, b, **kw)
+    np.testing.assert_array_equal(r1["q"], r4["q"])
