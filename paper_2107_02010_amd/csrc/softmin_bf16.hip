@@ -26,9 +26,14 @@
 // rewritten when its column potential changes (k_u_slots), so staging a tile
 // is a plain copy, prefetched into registers one tile ahead.
 // The reference changes only when the cluster changes (same level, re-rounded)
-// or, for the whole wave at once, when a row's sum would leave [2^-60, 2^60)
-// (first mass, overflow, underflow): then the block's maximum sets the new level and the
-// block is re-summed from the accumulators.
+// or, for the whole wave at once, when a row's sum would leave [2^-4, 2^59)
+// (first mass, overflow): then the larger of the block's maximum and the sum
+// so far sets the new level and the block is re-summed from the accumulators.
+// A row that holds mass keeps a sum >= 2^-4 (sums only grow; a cluster change
+// re-rounds the level by far less), so once every row of a wave holds mass the per-half
+// overflow test runs, and a block whose terms all lie below 2^-48 of the level
+// is skipped after its products (it cannot move any row sum beyond rounding);
+// the products of every pair are still computed.
 //
 // Padding and zero-weight columns use a finite sentinel (-1e30) rather than
 // -inf so that the lo products stay finite (-inf * 0 would be NaN).
@@ -40,8 +45,21 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kMasked = -1.0e30f;
+// log2 of the largest term a block may hold and still be skipped: with the row
+// sum >= 2^-4, a million columns of such terms move it by < 2^-24 relative.
+constexpr float kNegligible = -48.0f;
 
 static __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+static __device__ __forceinline__ float xor32_sum(float v) {
+    const unsigned u = __float_as_uint(v);
+    const auto t = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+static __device__ __forceinline__ float xor32_max(float v) {
+    const unsigned u = __float_as_uint(v);
+    const auto t = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return fmaxf(__uint_as_float(t[0]), __uint_as_float(t[1]));
+}
 
 template <int KP>
 __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
@@ -52,7 +70,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     constexpr int NCH = kColsPerTile * V16 / 256;  // chunks per thread per plane and tile
     constexpr int NBT = kColsPerTile / 32;         // 32-column blocks per tile
     constexpr int NCE = NBT * KP;                  // centroid floats per tile
-    static_assert(NCE <= 256, "one centroid float per thread");
+    constexpr int NCP = (NCE + 255) / 256;           // centroid floats per thread
     __shared__ __attribute__((aligned(16))) unsigned char lhi[kColsPerTile * RSB];
     __shared__ __attribute__((aligned(16))) unsigned char llo[kColsPerTile * RSB];
     __shared__ float lcent[NBT][KP];
@@ -133,6 +151,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     // running reference R (exact: R = shift - w) and the lane's sum relative to it
     float R = 0.0f, Sl = 0.0f, shift = 0.0f;
     int cur_cluster = -1;
+    bool mass = false, all_mass = false;
     // w = w_hi + w_lo (16 significant bits) rides in slot KP-1 of both row planes;
     // returns the reference the contraction now subtracts
     auto set_ref = [&](float target) -> float {
@@ -151,7 +170,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     // of 32 (clusters are padded), so a 32-column block is either fully inside
     // the range or skipped.
     uint4 pfh[NCH], pfl[NCH];
-    float pfc = 0.0f;
+    float pfc[NCP];
     int pfk = -1;
     auto next_tile = [&](int &r, int &a, int &e) -> bool {
         if (r >= 0 && a + kColsPerTile < e) {
@@ -181,9 +200,11 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
                 pfl[k] = *reinterpret_cast<const uint4 *>(clo + ((size_t)j * KP + v * 8) * 2);
             }
         }
-        if (tid < NCE) {
-            const int t = tid / KP;
-            pfc = a + 32 * t < e ? blk_cent[(size_t)((a >> 5) + t) * KP + (tid - t * KP)] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) {
+            const int q = tid + 256 * c;
+            const int t = q / KP;
+            pfc[c] = q < NCE && a + 32 * t < e ? blk_cent[(size_t)((a >> 5) + t) * KP + (q - t * KP)] : 0.0f;
         }
         if (tid < NBT) pfk = a + 32 * tid < e ? blk_cluster[(a >> 5) + tid] : -1;
     };
@@ -200,7 +221,11 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
             *reinterpret_cast<uint4 *>(lhi + c * RSB + v * 16) = pfh[k];
             *reinterpret_cast<uint4 *>(llo + c * RSB + v * 16) = pfl[k];
         }
-        if (tid < NCE) lcent[tid / KP][tid % KP] = pfc;
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) {
+            const int q = tid + 256 * c;
+            if (q < NCE) lcent[q / KP][q % KP] = pfc[c];
+        }
         if (tid < NBT) lcl[tid] = pfk;
         const int cj0 = j0, cend = jend;
         const bool more = next_tile(ri, j0, jend);
@@ -209,13 +234,13 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
 
         const int nblk = wave_active ? min(NBT, (cend - cj0 + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
-            const int cl = lcl[jb];
+            const int cl = __builtin_amdgcn_readfirstlane(lcl[jb]);
             if (cl != cur_cluster) {  // wave-uniform: new cluster shift, same reference level
                 cur_cluster = cl;
                 float r = 0.0f;
 #pragma unroll
                 for (int t = 0; t < H; ++t) r = fmaf(xf[t], lcent[jb][h * H + t], r);
-                shift = r + __shfl_xor(r, 32, 64);
+                shift = xor32_sum(r);
                 const float Rn = set_ref(shift - R);
                 Sl = Sl > 0.0f ? Sl * fast_exp2(R - Rn) : 0.0f;
                 R = Rn;
@@ -232,7 +257,17 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh[s], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[s], acc, 0, 0, 0);
             }
-            // acc[r] = s_ij - R; pairwise sum keeps the add chain short
+            // acc[r] = s_ij - R.  Once every row of the wave holds mass (its sum is
+            // >= 2^-4 relative to R), a block whose terms are all below 2^kNegligible
+            // cannot change any row sum beyond FP32 rounding: its exponentials are
+            // skipped (wave-uniform test on the block maximum).
+            if (all_mass) {
+                float mx = acc[0];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+                if (!__any(mx > kNegligible)) continue;
+            }
+            // pairwise sum keeps the add chain short
             float ex[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) ex[r] = fast_exp2(acc[r]);
@@ -241,14 +276,15 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
 #pragma unroll
                 for (int r = 0; r < w; ++r) ex[r] += ex[r + w];
             float Sn = Sl + ex[0];
-            const float Sc = Sn + __shfl_xor(Sn, 32, 64);
-            const bool need = !(Sc < 0x1p60f) || !(Sc >= 0x1p-60f);
+            if (__any(!(Sn < 0x1p59f) || !mass)) {  // wave-uniform: look at whole rows
+            const float Sc = xor32_sum(Sn);
+            const bool need = !(Sc < 0x1p59f) || !(Sc >= 0x1p-4f);
             if (__any(need)) {  // wave-uniform: re-level the rows that need it
                 float tmax = acc[0];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
-                tmax = fmaxf(tmax, __shfl_xor(tmax, 32, 64));
-                const float So = Sl + __shfl_xor(Sl, 32, 64);
+                tmax = xor32_max(tmax);
+                const float So = xor32_sum(Sl);
                 const float lg = So > 0.0f ? __log2f(So) : -__builtin_huge_valf();
                 const float top = fmaxf(tmax, lg);  // new level relative to R
                 if (need && top > 0.5f * kMasked) {
@@ -261,13 +297,16 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
                     R = Rn;
                 }
             }
+            mass = xor32_sum(Sn) >= 0x1p-4f;
+            all_mass = !__any(!mass);
+            }
             Sl = Sn;
         }
         have = more;
     }
 
     // both lane halves of a row share R: the row's partial is (R, sum of both halves)
-    const float Sr = Sl + __shfl_xor(Sl, 32, 64);
+    const float Sr = xor32_sum(Sl);
     const float M = Sr > 0.0f ? R : -__builtin_huge_valf();
     if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, Sr);
 }
