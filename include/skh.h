@@ -84,6 +84,12 @@ typedef struct skh_params {
                             <= 0: keep every block */
     double start_scale;  /* init != COLD: largest scale of the schedule (start_scale q^k, then
                             blur); <= 0: the diameter rule.  A cold run ignores it */
+    const int32_t *labels_x; /* clustered paths (BF16 split, multiscale): optional cluster label
+                            of every point of x in [0, k) (device, n values), k = n_clusters or
+                            ceil(sqrt(n)); replaces the K-means (points are grouped, centres
+                            are their weighted means).  Both or neither.  SKH_EINVAL when a
+                            label is out of range */
+    const int32_t *labels_y; /* the same for y (m values) */
     int32_t extra_iters; /* iterations at sigma = blur after the scale list (>= 0) */
     int32_t max_iters;   /* converged mode: at most this many iterations after the list */
     int32_t check_every; /* converged mode: marginal-error check period (>= 1) */

@@ -96,7 +96,8 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
                         init=None, potentials: bool = False, timing: bool = False,
                         multiscale: bool = False, jump_scale: float = 0.0,
                         trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10,
-                        start_scale: float = 0.0, checked_init: bool = False, fixed: int = 0):
+                        start_scale: float = 0.0, checked_init: bool = False, fixed: int = 0,
+                        labels=None):
     """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
 
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
@@ -104,7 +105,9 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     init: optional (f, g, p, q) starting potentials; the schedule then starts at start_scale
     (<= 0: the diameter rule).  checked_init=True: non-finite starting values are discarded
     and the call runs cold (stats["warm_fallback"] = 1).  fixed: SKH_FIX_* bits of the loops
-    whose vectors are inputs (taken from init) and stay as given.  With potentials=True returns
+    whose vectors are inputs (taken from init) and stay as given.  labels: optional (labels_x,
+    labels_y) int32 cluster labels that replace the K-means on the clustered paths.
+    With potentials=True returns
     (S, dict(f=..., g=..., p=..., q=...), stats dict), else S (a Python float).
     timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
     multiscale=True: K-means coarse phase while sigma > jump_scale (0: RMS cluster radius,
@@ -133,6 +136,14 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     P.n_clusters = int(n_clusters)
     P.kmeans_iters = int(kmeans_iters)
     P.fixed = int(fixed)
+    if labels is not None:
+        lx, ly = labels
+        for t, k, nm in ((lx, n, "labels_x"), (ly, m, "labels_y")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+                    and t.is_contiguous() and t.numel() == k):
+                raise ValueError(f"{nm} must be a contiguous int32 CUDA tensor of {k} values")
+        P.labels_x = lx.data_ptr()
+        P.labels_y = ly.data_ptr()
     if fixed and init is None:
         raise ValueError("fixed dual vectors are passed through init=(f, g, p, q)")
     dev = x.device

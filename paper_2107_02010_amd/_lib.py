@@ -41,6 +41,7 @@ class SkhParams(ctypes.Structure):
     _fields_ = [
         ("blur", _c_d), ("reach", _c_d), ("scaling", _c_d), ("diameter", _c_d), ("tol", _c_d),
         ("jump_scale", _c_d), ("trunc_theta", _c_d), ("start_scale", _c_d),
+        ("labels_x", _c_vp), ("labels_y", _c_vp),
         ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
         ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("multiscale", _c_i32),
         ("n_clusters", _c_i32), ("kmeans_iters", _c_i32), ("fixed", _c_i32),

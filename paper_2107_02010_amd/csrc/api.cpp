@@ -74,9 +74,13 @@ struct Clustered {
 
 // K-means of a packed cloud and the padded cluster sizes (poff[k] = n_pad).
 int cluster_start(skh_ctx *ctx, Clustered &cl, const float *X, const float *w, int kp, int iters,
-                  hipStream_t s) {
-    SKH_HIP(skh::run_kmeans(X, w, cl.n, kp, cl.k, iters, cl.C, cl.cmass, cl.radius, cl.kws,
-                            &cl.perm, &cl.off, s));
+                  hipStream_t s, const int *labels = nullptr) {
+    if (labels)
+        SKH_HIP(skh::clusters_from_labels(X, w, cl.n, kp, cl.k, labels, cl.C, cl.cmass, cl.radius,
+                                          cl.kws, &cl.perm, &cl.off, s));
+    else
+        SKH_HIP(skh::run_kmeans(X, w, cl.n, kp, cl.k, iters, cl.C, cl.cmass, cl.radius, cl.kws,
+                                &cl.perm, &cl.off, s));
     SKH_HIP(skh::build_padded_layout(cl.perm, cl.off, cl.k, cl.psize, cl.poff, cl.ssum, s));
     return SKH_OK;
 }
@@ -312,6 +316,8 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (P.init != SKH_INIT_COLD && P.init != SKH_INIT_GIVEN && P.init != SKH_INIT_WARM)
         return fail(ctx, SKH_EINVAL, "unknown init mode");
     if (std::isnan(P.start_scale)) return fail(ctx, SKH_EINVAL, "NaN parameter");
+    if ((P.labels_x == nullptr) != (P.labels_y == nullptr))
+        return fail(ctx, SKH_EINVAL, "labels_x and labels_y go together");
     if (P.init && (!f || !g || !p || !q))
         return fail(ctx, SKH_EINVAL, "init requires f, g, p and q");
     const bool split = P.precision == SKH_BF16_SPLIT;
@@ -419,9 +425,18 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     int t_jump = 0;
     if (clustered) {
         const int kmi = P.kmeans_iters;
-        int rc = cluster_start(ctx, cx, Xp, a, kp, kmi, s);
+        if (P.labels_x) {  // given clusterings: check the labels before sorting by them
+            SKH_HIP(hipMemsetAsync(wbad, 0, sizeof(int), s));
+            SKH_HIP(skh::launch_check_labels(P.labels_x, (int)n, cx.k, wbad, s));
+            SKH_HIP(skh::launch_check_labels(P.labels_y, (int)m, cy.k, wbad, s));
+            SKH_HIP(hipMemcpyAsync(hb + 544, wbad, sizeof(int), hipMemcpyDeviceToHost, s));
+            SKH_HIP(hipStreamSynchronize(s));
+            if (*reinterpret_cast<const int *>(hb + 544))
+                return fail(ctx, SKH_EINVAL, "cluster label out of range");
+        }
+        int rc = cluster_start(ctx, cx, Xp, a, kp, kmi, s, P.labels_x);
         if (rc) return rc;
-        rc = cluster_start(ctx, cy, Yp, b, kp, kmi, s);
+        rc = cluster_start(ctx, cy, Yp, b, kp, kmi, s, P.labels_y);
         if (rc) return rc;
         Clustered *cl2[2] = {&cx, &cy};
         for (Clustered *cl : cl2) {

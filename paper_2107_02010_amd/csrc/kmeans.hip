@@ -495,3 +495,24 @@ hipError_t sort_labels(int n, int k, int *ws, int **perm_out, int **off_out, hip
 }
 
 }  // namespace skh
+
+namespace skh {
+
+// The clustering of run_kmeans from given labels (in [0, k), checked by the
+// caller): stable sort by label, weighted means and radii, no Lloyd iterations.
+hipError_t clusters_from_labels(const float *X, const float *w, int n, int kp, int k,
+                                const int *labels, float *C, float *cmass, float *radius, int *ws,
+                                int **perm_out, int **off_out, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(ws, labels, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    int *perm, *off;
+    e = sort_labels(n, k, ws, &perm, &off, s);
+    if (e != hipSuccess) return e;
+    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C, cmass);
+    if (radius) SKH_KP_DISPATCH(kp, k_cluster_radius, dim3(k), dim3(kT), 0, s, X, perm, off, C, radius);
+    *perm_out = perm;
+    *off_out = off;
+    return hipGetLastError();
+}
+
+}  // namespace skh

@@ -248,6 +248,10 @@ hipError_t launch_expand(const int *lab, int64_t n, const float *pred, int k, do
 hipError_t launch_labels_from_perm(const int *perm, const int *off, int k, int *lab, hipStream_t s);
 hipError_t launch_nonfinite(const float *v, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_check_labels(const int *lab, int n, int k, int *bad, hipStream_t s);
+// The clustering of run_kmeans from given labels in [0, k): sort, means, radii.
+hipError_t clusters_from_labels(const float *X, const float *w, int n, int kp, int k,
+                                const int *labels, float *C, float *cmass, float *radius, int *ws,
+                                int **perm_out, int **off_out, hipStream_t s);
 // Stable counting sort of the labels in ws[0, n) (K-means workspace layout).
 hipError_t sort_labels(int n, int k, int *ws, int **perm_out, int **off_out, hipStream_t s);
 

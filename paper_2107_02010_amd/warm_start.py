@@ -217,14 +217,17 @@ def make_example(x, a, y, b, blur: float, n_clusters: int = 0, kmeans_iters: int
 
 
 def predict_potentials(net: WarmStartNet, x, a, y, b, blur: float, precision: str = "bf16x3",
-                       n_clusters: int = 0, kmeans_iters: int = 10):
-    """Starting (f, g, p, q) for the pair from the network's cluster predictions."""
+                       n_clusters: int = 0, kmeans_iters: int = 10, return_labels: bool = False):
+    """Starting (f, g, p, q) for the pair from the network's cluster predictions (and the
+    cluster labels of the two clouds when return_labels)."""
     tk = cluster_tokens(x, a, y, b, n_clusters, kmeans_iters)
     batch = TokenBatch(tk["tokens"], tk["w"], [0, tk["kx"], tk["kx"] + tk["ky"]])
     pred = net.forward(batch, precision)
     s2 = blur * blur
     f, p = expand(tk["labels_x"], tk["kx"], pred[:tk["kx"]], s2)
     g, q = expand(tk["labels_y"], tk["ky"], pred[tk["kx"]:], s2)
+    if return_labels:
+        return (f, g, p, q), (tk["labels_x"], tk["labels_y"])
     return f, g, p, q
 
 
@@ -236,9 +239,12 @@ def sinkhorn_divergence_warm(net: WarmStartNet, x, a, y, b, blur: float, scaling
     predictions make the solver run cold (stats["warm_fallback"] = 1).  Returns
     (S, potentials, stats) like sinkhorn_divergence(..., potentials=True)."""
     s = net.meta.get("start_steps", 5) if start_steps is None else start_steps
-    f, g, p, q = predict_potentials(net, x, a, y, b, blur, net_precision, n_clusters, kmeans_iters)
+    init, labels = predict_potentials(net, x, a, y, b, blur, net_precision, n_clusters,
+                                      kmeans_iters, return_labels=True)
     kw.pop("potentials", None)
-    return sinkhorn_divergence(x, a, y, b, blur=blur, scaling=scaling, init=(f, g, p, q),
+    # the solver's clustered layout reuses the token clustering (same K-means on the
+    # same packed points) instead of running the K-means again
+    return sinkhorn_divergence(x, a, y, b, blur=blur, scaling=scaling, init=init,
                                start_scale=blur / scaling ** s, checked_init=True,
                                potentials=True, n_clusters=n_clusters, kmeans_iters=kmeans_iters,
-                               **kw)
+                               labels=labels, **kw)

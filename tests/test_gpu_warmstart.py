@@ -318,3 +318,28 @@ def test_trained_network_gains_on_fresh_pairs():
         cold_it += st0["iters"]
         warm_it += st1["iters"]
     assert warm_it < 0.5 * cold_it, (warm_it, cold_it)
+
+
+@pytest.mark.parametrize("multiscale,precision", [(False, "bf16x3"), (True, "fp32"), (True, "bf16x3")])
+def test_given_labels_reproduce_the_kmeans_clustering(multiscale, precision):
+    """The token clustering is the solver's own K-means: handing its labels to the solver
+    (which then skips the K-means) gives the same solve bit for bit."""
+    import torch
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd.warm_start import cluster_tokens
+    x, a, y, b = synth.fiber_pair(6000, 20, 77)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.8, multiscale=multiscale, precision=precision,
+              extra_iters=3)
+    note(f"given labels multiscale={multiscale} {precision}")
+    S0, pot0, st0 = skh.sinkhorn_divergence(X, A, Y, B, potentials=True, **kw)
+    tk = cluster_tokens(X, A, Y, B)
+    S1, pot1, st1 = skh.sinkhorn_divergence(X, A, Y, B, potentials=True,
+                                            labels=(tk["labels_x"], tk["labels_y"]), **kw)
+    assert S1 == S0 and st1["iters"] == st0["iters"]
+    for k in ("f", "g", "p", "q"):
+        assert torch.equal(pot0[k], pot1[k])
+    bad = tk["labels_x"].clone()
+    bad[5] = 10_000
+    with pytest.raises(skh.SkhError):
+        skh.sinkhorn_divergence(X, A, Y, B, labels=(bad, tk["labels_y"]), **kw)
