@@ -73,62 +73,110 @@ hipError_t launch_centroid_dist(const float *CI, int ki, const float *CJ, int kj
     return hipGetLastError();
 }
 
-// One thread per row cluster I: the kept column ranges (padded order) and the
-// number of real point pairs they hold (added to *pairs).
-__global__ __launch_bounds__(kT) void k_block_ranges(
+// One workgroup per row cluster I: the kept column ranges (padded order) and the
+// number of real point pairs they hold (added to *pairs).  Thread t owns the
+// column clusters [t CH, (t+1) CH).  A cluster is in a run when it is kept or
+// empty (an empty cluster has no columns, so it never breaks a run); run starts
+// and ends are found in parallel and the i-th start pairs with the i-th end.
+constexpr int kBR = 256;
+
+__global__ __launch_bounds__(kBR) void k_block_ranges(
     int ki, int kj, const float *__restrict__ rmax, const float *__restrict__ cmax,
     const float *__restrict__ dist, const float *__restrict__ rrad, const float *__restrict__ crad,
     const int *__restrict__ cpoff, const int *__restrict__ coff, const int *__restrict__ roff,
     float inv_lam, float theta_eps, int keep_all, int cap, int2 *__restrict__ ranges,
     int *__restrict__ count, unsigned long long *__restrict__ pairs) {
-    const int I = blockIdx.x * kT + threadIdx.x;
-    if (I >= ki) return;
+    const int I = blockIdx.x, t = threadIdx.x;
+    __shared__ float sbs[kBR];
+    __shared__ int sbj[kBR];
+    __shared__ int sst[kBR], sen[kBR];
+    __shared__ long long scols[kBR];
     const float fm = rmax[I];
-    int2 *out = ranges + (size_t)I * cap;
     const long long rows_real = roff[I + 1] - roff[I];
-    if (!(fm > -finf()) || rows_real == 0) {
-        count[I] = 0;
+    if (!(fm > -finf()) || rows_real == 0) {  // uniform over the workgroup
+        if (t == 0) count[I] = 0;
         return;
     }
+    const int CH = (kj + kBR - 1) / kBR;
+    const int J0 = min(kj, t * CH), J1 = min(kj, J0 + CH);
     auto score = [&](int J) -> float {
         const float gm = cmax[J];
         if (!(gm > -finf())) return -finf();
         const float gap = fmaxf(0.0f, dist[(size_t)I * kj + J] - rrad[I] - crad[J]);
         return fmaxf(fm * inv_lam + gm, fm + gm * inv_lam) - 0.5f * gap * gap;
     };
-    int best = -1;
+    // the best block (first maximum in column order) is always kept
     float bs = -finf();
-    if (!keep_all) {
-        for (int J = 0; J < kj; ++J) {
+    int bj = -1;
+    if (!keep_all)
+        for (int J = J0; J < J1; ++J) {
             const float sc = score(J);
             if (sc > bs) {
                 bs = sc;
-                best = J;
+                bj = J;
             }
         }
-    }
-    int n = 0, run_begin = -1, run_end = -1;
-    long long cols_real = 0;
-    for (int J = 0; J < kj; ++J) {
-        const int pb = cpoff[J], pe = cpoff[J + 1];
-        if (pe == pb) continue;  // empty cluster: does not break a run
-        const bool keep = keep_all || J == best || score(J) >= -theta_eps;
-        if (keep) {
-            cols_real += coff[J + 1] - coff[J];
-            if (run_begin < 0) run_begin = pb;
-            run_end = pe;
-        } else if (run_begin >= 0) {
-            if (n < cap) out[n] = make_int2(run_begin, run_end);
-            ++n;
-            run_begin = -1;
+    sbs[t] = bs;
+    sbj[t] = bj;
+    __syncthreads();
+    for (int o = kBR / 2; o >= 1; o >>= 1) {  // ties keep the lower thread: the lower J
+        if (t < o && sbs[t + o] > sbs[t]) {
+            sbs[t] = sbs[t + o];
+            sbj[t] = sbj[t + o];
         }
+        __syncthreads();
     }
-    if (run_begin >= 0) {
-        if (n < cap) out[n] = make_int2(run_begin, run_end);
-        ++n;
+    const int best = sbj[0];
+    auto in_run = [&](int J) -> bool {
+        if (cpoff[J + 1] == cpoff[J]) return true;  // empty
+        return keep_all || J == best || score(J) >= -theta_eps;
+    };
+    // starts, ends and real columns of this thread's clusters
+    int nst = 0, nen = 0;
+    long long cols = 0;
+    bool prev = J0 > 0 ? in_run(J0 - 1) : false;
+    for (int J = J0; J < J1; ++J) {
+        const bool cur = in_run(J);
+        const bool next = J + 1 < kj ? in_run(J + 1) : false;
+        nst += cur && !prev;
+        nen += cur && !next;
+        if (cur && cpoff[J + 1] > cpoff[J]) cols += coff[J + 1] - coff[J];
+        prev = cur;
     }
-    count[I] = min(n, cap);
-    atomicAdd(pairs, (unsigned long long)(rows_real * cols_real));
+    sst[t] = nst;
+    sen[t] = nen;
+    scols[t] = cols;
+    __syncthreads();
+    // exclusive scans of the start and end counts (Hillis-Steele), sum of columns
+    for (int o = 1; o < kBR; o <<= 1) {
+        const int a = t >= o ? sst[t - o] : 0, b = t >= o ? sen[t - o] : 0;
+        const long long c = t >= o ? scols[t - o] : 0;
+        __syncthreads();
+        sst[t] += a;
+        sen[t] += b;
+        scols[t] += c;
+        __syncthreads();
+    }
+    int rs = sst[t] - nst, re = sen[t] - nen;  // ranks of this thread's first start / end
+    int2 *out = ranges + (size_t)I * cap;
+    prev = J0 > 0 ? in_run(J0 - 1) : false;
+    for (int J = J0; J < J1; ++J) {
+        const bool cur = in_run(J);
+        const bool next = J + 1 < kj ? in_run(J + 1) : false;
+        if (cur && !prev) {
+            if (rs < cap) out[rs].x = cpoff[J];
+            ++rs;
+        }
+        if (cur && !next) {
+            if (re < cap) out[re].y = cpoff[J + 1];
+            ++re;
+        }
+        prev = cur;
+    }
+    if (t == kBR - 1) {
+        count[I] = min(sst[kBR - 1], cap);
+        atomicAdd(pairs, (unsigned long long)(rows_real * scols[kBR - 1]));
+    }
 }
 
 hipError_t launch_block_ranges(int ki, int kj, const float *rmax, const float *cmax,
@@ -136,9 +184,10 @@ hipError_t launch_block_ranges(int ki, int kj, const float *rmax, const float *c
                                const int *cpoff, const int *coff, const int *roff, double lam,
                                double theta_eps, int keep_all, int cap, int2 *ranges, int *count,
                                unsigned long long *pairs, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_ranges, dim3((ki + kT - 1) / kT), dim3(kT), 0, s, ki, kj, rmax, cmax,
-                       dist, rrad, crad, cpoff, coff, roff, (float)(1.0 / lam), (float)theta_eps,
-                       keep_all, cap, ranges, count, pairs);
+    if (ki <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_ranges, dim3(ki), dim3(kBR), 0, s, ki, kj, rmax, cmax, dist, rrad,
+                       crad, cpoff, coff, roff, (float)(1.0 / lam), (float)theta_eps, keep_all, cap,
+                       ranges, count, pairs);
     return hipGetLastError();
 }
 
