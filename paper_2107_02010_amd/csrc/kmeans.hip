@@ -18,42 +18,74 @@ namespace skh {
 
 constexpr int kT = 256;
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Nearest centre of every point, ties to the lowest centre index.  The
+// distance is ranked by 1/2 |c|^2 - <x, c> (the |x|^2 term is common to a row),
+// computed on the matrix cores like the softmin's contraction: each wave keeps
+// 32 rows as the B operand of v_mfma_f32_32x32x2f32 in VGPRs, with the unused
+// last slot set to 1; tiles of 128 centres are staged in LDS as -c with
+// 1/2 |c|^2 in that slot, so the MFMA output is the ranking value itself.
+// Each lane keeps the running minimum of its 16 centres per block; the two
+// lane halves of a row combine once at the end.  Rows padded to KP have their
+// slots past the coordinates at zero, so slot KP - 1 is free.
 template <int KP>
-__global__ __launch_bounds__(kT) void k_kmeans_assign(const float *__restrict__ X, int n,
-                                                      const float *__restrict__ C, int k,
-                                                      int *__restrict__ label) {
-    constexpr int CB = 32;  // centroids per LDS chunk
-    __shared__ float sc[CB][KP];
-    __shared__ float scn[CB];
-    const int i = blockIdx.x * kT + threadIdx.x;
-    float xr[KP];
+__global__ __launch_bounds__(256) void k_kmeans_assign(const float *__restrict__ X, int n,
+                                                       const float *__restrict__ C, int k,
+                                                       int *__restrict__ label) {
+    constexpr int H = KP / 2;       // k-steps per block; lane half h holds slots [h H, h H + H)
+    constexpr int STRIDE = KP + 4;  // LDS row stride (floats)
+    constexpr int TCN = 128;        // centres per tile
+    __shared__ float tile[TCN * STRIDE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, li = lane & 31;
+    const int i = blockIdx.x * 128 + wave * 32 + li;
+    const int ic = i < n ? i : n - 1;
+    float xr[H];
 #pragma unroll
-    for (int d = 0; d < KP; ++d) xr[d] = i < n ? X[(size_t)i * KP + d] : 0.0f;
+    for (int s = 0; s < H; ++s) {
+        const int slot = h * H + s;
+        xr[s] = slot == KP - 1 ? 1.0f : X[(size_t)ic * KP + slot];
+    }
     float best = __builtin_huge_valf();
-    int bl = 0;
-    for (int c0 = 0; c0 < k; c0 += CB) {
+    int bj = 0x7fffffff;
+    for (int c0 = 0; c0 < k; c0 += TCN) {
         __syncthreads();
-        const int cnt = min(CB, k - c0);
-        for (int e = threadIdx.x; e < cnt * KP; e += kT) sc[e / KP][e % KP] = C[(size_t)c0 * KP + e];
-        __syncthreads();
-        if (threadIdx.x < cnt) {
-            float s = 0.0f;
-#pragma unroll
-            for (int d = 0; d < KP; ++d) s = fmaf(sc[threadIdx.x][d], sc[threadIdx.x][d], s);
-            scn[threadIdx.x] = 0.5f * s;
+        for (int e = tid; e < TCN * KP; e += 256) {
+            const int c = e / KP, dd = e - c * KP;
+            tile[c * STRIDE + dd] = c0 + c < k ? -C[(size_t)(c0 + c) * KP + dd] : 0.0f;
         }
         __syncthreads();
-        for (int c = 0; c < cnt; ++c) {
-            float v = scn[c];
+        if (tid < TCN) {
+            float sq = 0.0f;
 #pragma unroll
-            for (int d = 0; d < KP; ++d) v = fmaf(-xr[d], sc[c][d], v);
-            if (v < best) {
-                best = v;
-                bl = c0 + c;
+            for (int dd = 0; dd < KP - 1; ++dd) sq = fmaf(tile[tid * STRIDE + dd], tile[tid * STRIDE + dd], sq);
+            // a missing centre gets a value no real one can exceed
+            tile[tid * STRIDE + KP - 1] = c0 + tid < k ? 0.5f * sq : 1.0e30f;
+        }
+        __syncthreads();
+        const int nblk = min(TCN / 32, (k - c0 + 31) >> 5);
+        for (int jb = 0; jb < nblk; ++jb) {
+            v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float *tp = &tile[(jb * 32 + li) * STRIDE + h * H];
+#pragma unroll
+            for (int s = 0; s < H; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[s], xr[s], acc, 0, 0, 0);
+            // output register r of lane half h holds centre 8 (r / 4) + 4 h + r % 4 of the
+            // block: increasing in r, so a strict comparison keeps the lowest index
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (acc[r] < best) {
+                    best = acc[r];
+                    bj = c0 + jb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                }
             }
         }
     }
-    if (i < n) label[i] = bl;
+    const float ob = __shfl_xor(best, 32, 64);
+    const int oj = __shfl_xor(bj, 32, 64);
+    if (ob < best || (ob == best && oj < bj)) bj = oj;
+    if (h == 0 && i < n) label[i] = bj;
 }
 
 // counts[c * nb + b] = number of points of block b (kT points) with label c.
@@ -390,7 +422,8 @@ hipError_t run_kmeans(const float *X, const float *w, int n, int kp, int k, int 
     hipLaunchKernelGGL(k_init_centroids, dim3(blocks((int64_t)k * kp)), dim3(kT), 0, s, X, n, k, kp,
                        C);
     for (int it = 0; it <= iters; ++it) {
-        SKH_KP_DISPATCH(kp, k_kmeans_assign, dim3(blocks(n)), dim3(kT), 0, s, X, n, C, k, label);
+        SKH_KP_DISPATCH(kp, k_kmeans_assign, dim3((n + 127) / 128), dim3(256), 0, s, X, n, C, k,
+                        label);
         hipLaunchKernelGGL(k_label_count, dim3(nb), dim3(kT), k * sizeof(int), s, label, n, k, nb,
                            counts);
         hipError_t e = launch_exclusive_scan(counts, len, sums, offs, s);
