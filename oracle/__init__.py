@@ -73,6 +73,8 @@ def _load():
             lib.oracle_plan_apply.restype = None
             lib.oracle_grad_x.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _P, _D, _P]
             lib.oracle_grad_x.restype = None
+            lib.oracle_grad_weights.argtypes = [_I64, _P, _P, _D, _D, _P]
+            lib.oracle_grad_weights.restype = None
             _lib = lib
     return _lib
 
@@ -220,6 +222,21 @@ def grad_x(x, a, y, b, f, g, p, eps):
     out = np.empty_like(x)
     _load().oracle_grad_x(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y), _ptr(b),
                           _ptr(f), _ptr(g), _ptr(p), float(eps), _ptr(out))
+    return out
+
+
+def grad_y(x, a, y, b, f, g, q, eps):
+    """Gradient of S with respect to y: the x formula with the roles of the two
+    measures exchanged (S is symmetric in (alpha, beta))."""
+    return grad_x(y, b, x, a, g, f, q, eps)
+
+
+def grad_weights(f, p, blur, reach=None):
+    """dS/d alpha_i from (f, p) (dS/d beta_j from (g, q)): (rho + eps)(e^{-p/rho} - e^{-f/rho}),
+    f - p when balanced (envelope theorem on the dual of eq. (3), Section 2)."""
+    f, p = _f64(f), _f64(p)
+    out = np.empty_like(f)
+    _load().oracle_grad_weights(f.size, _ptr(f), _ptr(p), float(blur), _reach(reach), _ptr(out))
     return out
 
 

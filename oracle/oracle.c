@@ -367,6 +367,27 @@ void oracle_plan_apply(int64_t n, int64_t m, int d, const double *x, const doubl
     }
 }
 
+/* Derivative of S with respect to the weight alpha_i, from the dual vectors.
+ * The envelope theorem on the dual of eq. (3) gives, for OT(alpha, beta) at its
+ * optimal (f, g), d/d alpha_i = rho (1 - e^{-f_i/rho}) + eps sum_j beta_j (1 -
+ * exp((f_i + g_j - C_ij)/eps)); the optimality condition in f_i turns the sum
+ * into eps (m_beta - e^{-f_i/rho}).  OT(alpha, alpha) carries alpha in both
+ * slots (twice the same expression with p and m_alpha), and the mass term of
+ * eq. (5) adds eps (m_alpha - m_beta); in S the mass terms cancel:
+ *   dS/d alpha_i = (rho + eps) (e^{-p_i/rho} - e^{-f_i/rho}),
+ * evaluated as -(rho + eps) e^{-p_i/rho} expm1(-(f_i - p_i)/rho).  Balanced
+ * (rho -> infinity): f_i - p_i.  The same with (g, q) gives dS/d beta_j. */
+void oracle_grad_weights(int64_t n, const double *f, const double *p, double blur, double reach,
+                         double *out) {
+    double eps = blur * blur;
+    if (is_balanced(reach)) {
+        for (int64_t i = 0; i < n; ++i) out[i] = f[i] - p[i];
+        return;
+    }
+    double rho = reach * reach;
+    for (int64_t i = 0; i < n; ++i) out[i] = -(rho + eps) * exp(-p[i] / rho) * expm1(-(f[i] - p[i]) / rho);
+}
+
 /* Gradient of S with respect to the positions x_i, by the envelope theorem
  * applied to eq. (3) at the optimal dual vectors (the paper states that the
  * gradients are expressions of the four dual vectors):

@@ -431,6 +431,107 @@ def test_gradient_sum_and_dirac():
                                (x1 - y1) * math.exp(-C / (eps + 2 * rho)), rtol=1e-10)
 
 
+@pytest.mark.parametrize("reach", [None, 0.6])
+def test_gradient_y_finite_differences(reach):
+    rng = np.random.default_rng(28)
+    x, y = rng.uniform(size=(5, 2)), rng.uniform(size=(4, 2))
+    a, b = _w(5, 29), _u(4)
+    blur = 0.25
+    S, r = _conv(x, a, y, b, blur, reach, tol=1e-15)
+    G = oracle.grad_y(x, a, y, b, r["f"], r["g"], r["q"], blur ** 2)
+    h = 1e-5
+    fd = np.zeros_like(y)
+    for j in range(4):
+        for k in range(2):
+            yp, ym = y.copy(), y.copy()
+            yp[j, k] += h
+            ym[j, k] -= h
+            fd[j, k] = (_conv(x, a, yp, b, blur, reach, tol=1e-15)[0]
+                        - _conv(x, a, ym, b, blur, reach, tol=1e-15)[0]) / (2 * h)
+    np.testing.assert_allclose(G, fd, rtol=1e-5, atol=1e-9)
+
+
+def test_weight_gradient_finite_differences_unbalanced():
+    # Each weight moved alone (unbalanced: the masses need not agree).
+    rng = np.random.default_rng(31)
+    x, y = rng.uniform(size=(5, 2)), rng.uniform(size=(6, 2))
+    a, b = _w(5, 32), _w(6, 33, total=1.3)
+    blur, reach = 0.2, 0.6
+    S, r = _conv(x, a, y, b, blur, reach, tol=1e-15)
+    Ga = oracle.grad_weights(r["f"], r["p"], blur, reach)
+    Gb = oracle.grad_weights(r["g"], r["q"], blur, reach)
+    h = 1e-6
+    for i in range(5):
+        ap, am = a.copy(), a.copy()
+        ap[i] += h
+        am[i] -= h
+        fd = (_conv(x, ap, y, b, blur, reach, tol=1e-15)[0]
+              - _conv(x, am, y, b, blur, reach, tol=1e-15)[0]) / (2 * h)
+        assert fd == pytest.approx(Ga[i], rel=1e-6, abs=1e-10)
+    for j in range(6):
+        bp, bm = b.copy(), b.copy()
+        bp[j] += h
+        bm[j] -= h
+        fd = (_conv(x, a, y, bp, blur, reach, tol=1e-15)[0]
+              - _conv(x, a, y, bm, blur, reach, tol=1e-15)[0]) / (2 * h)
+        assert fd == pytest.approx(Gb[j], rel=1e-6, abs=1e-10)
+
+
+def test_weight_gradient_balanced_mass_preserving():
+    # Balanced: only mass-preserving moves stay feasible, and f, g carry a free constant;
+    # moving mass h from point k to point i changes S by h (G_i - G_k), free of that constant.
+    rng = np.random.default_rng(34)
+    x, y = rng.uniform(size=(5, 2)), rng.uniform(size=(6, 2))
+    a, b = _w(5, 35), _w(6, 36)
+    blur = 0.2
+    S, r = _conv(x, a, y, b, blur, None, tol=1e-15)
+    Ga = oracle.grad_weights(r["f"], r["p"], blur)
+    Gb = oracle.grad_weights(r["g"], r["q"], blur)
+    h = 1e-6
+    for i, k in ((0, 1), (2, 4), (3, 0)):
+        ap, am = a.copy(), a.copy()
+        ap[i] += h
+        ap[k] -= h
+        am[i] -= h
+        am[k] += h
+        fd = (_conv(x, ap, y, b, blur, None, tol=1e-15)[0]
+              - _conv(x, am, y, b, blur, None, tol=1e-15)[0]) / (2 * h)
+        assert fd == pytest.approx(Ga[i] - Ga[k], rel=1e-6, abs=1e-10)
+    for j, k in ((0, 5), (3, 2)):
+        bp, bm = b.copy(), b.copy()
+        bp[j] += h
+        bp[k] -= h
+        bm[j] -= h
+        bm[k] += h
+        fd = (_conv(x, a, y, bp, blur, None, tol=1e-15)[0]
+              - _conv(x, a, y, bm, blur, None, tol=1e-15)[0]) / (2 * h)
+        assert fd == pytest.approx(Gb[j] - Gb[k], rel=1e-6, abs=1e-10)
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 1.0), (0.6, 1.7), (2.0, 0.3)])
+def test_weight_gradient_dirac_closed_form(a, b):
+    # One Dirac each: dS/da and dS/db by central differences of the closed-form S of
+    # eq. (5) (minimiser of eq. (2) for one Dirac each, mass term included).
+    x, y = np.array([[0.3, -0.2]]), np.array([[-0.1, 0.4]])
+    C = 0.5 * ((x - y) ** 2).sum()
+    blur, reach = 0.3, 0.5
+    eps, rho = blur ** 2, reach ** 2
+
+    def S_closed(a, b):
+        return (_dirac_ot(a, b, C, eps, rho) - 0.5 * _dirac_ot(a, a, 0.0, eps, rho)
+                - 0.5 * _dirac_ot(b, b, 0.0, eps, rho) + 0.5 * eps * (a - b) ** 2)
+
+    h = 1e-5
+    da = (S_closed(a + h, b) - S_closed(a - h, b)) / (2 * h)
+    db = (S_closed(a, b + h) - S_closed(a, b - h)) / (2 * h)
+    S, r = _conv(x, [a], y, [b], blur, reach)
+    assert oracle.grad_weights(r["f"], r["p"], blur, reach)[0] == pytest.approx(da, rel=1e-8)
+    assert oracle.grad_weights(r["g"], r["q"], blur, reach)[0] == pytest.approx(db, rel=1e-8)
+    if a == b == 1.0:
+        # (eps + rho)(1 - e^{-C/(eps + 2 rho)}), differentiating the closed form by hand
+        assert da == pytest.approx((eps + rho) * (1 - math.exp(-C / (eps + 2 * rho))), rel=1e-8)
+
+
 # ------------------------------------------------------------- plan apply ----
 
 def test_plan_apply_marginal_and_labels():
