@@ -221,6 +221,28 @@ int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const fl
                const float *p, double blur, float *grad);
 
 /*
+ * All four gradients of S_{eps,rho}(alpha, beta) from the dual vectors of a
+ * converged solve (Section 2: the gradients with respect to alpha_i, x_i,
+ * beta_j, y_j are expressions of the four dual vectors f, p on alpha and g, q
+ * on beta):
+ *   grad_a_i = (rho + eps)(e^{-p_i/rho} - e^{-f_i/rho}), f_i - p_i when balanced
+ *              (envelope theorem on the dual of eq. (3) for the three OT terms
+ *              of eq. (5); the mass terms cancel); grad_b from (g, q);
+ *   grad_x   as skh_grad_x;  grad_y the same with the roles of the measures
+ *              exchanged: sum_i pi_ij (y_j - x_i) - sum_l pi^{bb}_jl (y_j - y_l).
+ * eps = blur^2, rho = reach^2; reach <= 0 or infinite: balanced (grad_a and
+ * grad_b are then defined up to one shared additive constant, the free constant
+ * of (f, g)).  Inputs: all required (device, caller order, as returned by
+ * skh_sinkhorn_divergence).  Outputs (device, FP32): grad_a (n), grad_b (m),
+ * grad_x (n x d), grad_y (m x d); each may be NULL and is then not computed.
+ * Errors: SKH_EINVAL for NULL inputs, sizes out of range, blur <= 0, NaN reach.
+ */
+int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                  const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                  const float *p, const float *q, double blur, double reach, float *grad_a,
+                  float *grad_b, float *grad_x, float *grad_y);
+
+/*
  * K-means coarse scale of one cloud (coarse-to-fine strategy, Section 2: a
  * K-means subsampling of the points for the first, coarse iterations).
  * Lloyd iterations from k evenly strided points (point floor(c n / k) for

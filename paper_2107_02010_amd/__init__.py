@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT, SKH_FIX_P, SKH_FIX_Q, SKH_FIX_CROSS  # noqa: F401
 
-__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "diameter",
+__all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "gradients",
+           "diameter",
            "self_potential",
            "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
 
@@ -280,29 +281,57 @@ def grad_x(x, a, y, b, f, g, p, blur: float) -> torch.Tensor:
     return out
 
 
+def gradients(x, a, y, b, pot, blur: float, reach=None, wrt=("a", "b", "x", "y")) -> dict:
+    """Gradients of S with respect to the weights and positions of both measures from
+    the dual vectors pot = {f, g, p, q} of a solve (Section 2: expressions of the four
+    dual vectors).  dS/da_i = (rho + eps)(e^{-p_i/rho} - e^{-f_i/rho}) (f_i - p_i when
+    balanced: then dS/da and dS/db share a free additive constant), dS/db likewise from
+    (g, q); dS/dx as grad_x, dS/dy with the roles exchanged.  wrt: which to compute."""
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    dev = x.device
+    a, b = _as_vec(a, n, "a", dev), _as_vec(b, m, "b", dev)
+    f, g = _as_vec(pot["f"], n, "f", dev), _as_vec(pot["g"], m, "g", dev)
+    p, q = _as_vec(pot["p"], n, "p", dev), _as_vec(pot["q"], m, "q", dev)
+    shapes = {"a": (n,), "b": (m,), "x": (n, d), "y": (m, d)}
+    out = {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in wrt}
+    rr = 0.0 if reach is None else float(reach)
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_gradients(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d, _ptr(f),
+                                   _ptr(g), _ptr(p), _ptr(q), float(blur), rr,
+                                   *(_ptr(out[k]) if k in out else None for k in "abxy"))
+    _lib.check(rc, ctx)
+    return out
+
+
 class SinkhornDivergence(torch.autograd.Function):
-    """S_eps(alpha, beta) as a differentiable function of the positions x.
+    """S_eps(alpha, beta) as a differentiable function of x, a, y and b.
 
     forward runs the solver (eq. (6) after the symmetric loop); backward calls the
-    hand-written gradient kernel with the saved dual vectors, without
+    hand-written gradient kernels with the saved dual vectors, without
     differentiating through the iterations (envelope theorem at the fixed point).
-    Only x receives a gradient."""
+    Balanced problems: the weight gradients carry the free constant of (f, g)."""
 
     @staticmethod
     def forward(ctx, x, a, y, b, kw):
         S, pot, st = sinkhorn_divergence(x, a, y, b, potentials=True, **kw)
-        ctx.save_for_backward(x, a, y, b, pot["f"], pot["g"], pot["p"])
+        ctx.save_for_backward(x, a, y, b, pot["f"], pot["g"], pot["p"], pot["q"])
         ctx.blur = kw.get("blur", 0.05)
+        ctx.reach = kw.get("reach", None)
         return torch.tensor(S, dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, gS):
-        x, a, y, b, f, g, p = ctx.saved_tensors
-        gx = None
-        if ctx.needs_input_grad[0]:
-            gx = grad_x(x.detach(), a, y, b, f, g, p, ctx.blur)
-            gx = (gx.to(torch.float64) * gS).to(x.dtype)
-        return gx, None, None, None, None
+        x, a, y, b, f, g, p, q = ctx.saved_tensors
+        want = [k for k, need in zip("xayb", ctx.needs_input_grad[:4]) if need]
+        res = {}
+        if want:
+            res = gradients(x.detach(), a.detach(), y.detach(), b.detach(),
+                            dict(f=f, g=g, p=p, q=q), ctx.blur, ctx.reach, wrt=tuple(want))
+        src = {"x": x, "a": a, "y": y, "b": b}
+        grads = [(res[k].to(torch.float64) * gS).to(src[k].dtype) if k in res else None
+                 for k in "xayb"]
+        return (*grads, None)
 
 
 def sinkhorn_loss(x, a, y, b, **kw):

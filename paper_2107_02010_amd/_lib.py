@@ -84,6 +84,8 @@ SIGNATURES = {
                                 _c_vp, _c_d, _c_vp, _c_i32, _c_i32, _c_vp, _c_vp]),
     "skh_grad_x": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp,
                             _c_vp, _c_d, _c_vp]),
+    "skh_gradients": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp,
+                               _c_vp, _c_vp, _c_vp, _c_d, _c_d, _c_vp, _c_vp, _c_vp, _c_vp]),
     "skh_kmeans": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp,
                             _c_vp, _c_vp, _c_vp]),
     "skh_diameter": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, ctypes.POINTER(_c_d)]),

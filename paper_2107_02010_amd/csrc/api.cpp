@@ -1023,6 +1023,35 @@ int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const fl
     return SKH_OK;
 }
 
+int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                  const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                  const float *p, const float *q, double blur, double reach, float *grad_a,
+                  float *grad_b, float *grad_x, float *grad_y) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !a || !y || !b || !f || !g || !p || !q) return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
+        return fail(ctx, SKH_EINVAL, "n, m out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    if (!(blur > 0.0) || !std::isfinite(blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
+    if (std::isnan(reach)) return fail(ctx, SKH_EINVAL, "reach is NaN");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = ctx->stream;
+    const double eps = blur * blur;
+    const double rho = (reach > 0.0 && std::isfinite(reach)) ? reach * reach : 0.0;
+    if (grad_a) SKH_HIP(skh::launch_grad_weights(f, p, n, eps, rho, grad_a, s));
+    if (grad_b) SKH_HIP(skh::launch_grad_weights(g, q, m, eps, rho, grad_b, s));
+    if (grad_x) {
+        const int rc = skh_grad_x(ctx, x, a, n, y, b, m, d, f, g, p, blur, grad_x);
+        if (rc) return rc;
+    }
+    if (grad_y) {
+        // S is symmetric in (alpha, beta): the x formula with the roles exchanged
+        const int rc = skh_grad_x(ctx, y, b, m, x, a, n, d, g, f, q, blur, grad_y);
+        if (rc) return rc;
+    }
+    return SKH_OK;
+}
+
 int skh_diameter(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
                  double *out) {
     if (!ctx) return SKH_EINVAL;

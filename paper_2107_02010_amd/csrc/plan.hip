@@ -281,4 +281,27 @@ hipError_t launch_grad_combine(const float *X, int n, int d, int kp, const float
     return hipGetLastError();
 }
 
+// dS/d alpha_i from the dual vectors (envelope theorem on the dual of eq. (3) for
+// the three OT terms of eq. (5); the mass terms cancel):
+//   (rho + eps)(e^{-p_i/rho} - e^{-f_i/rho}) = -(rho + eps) e^{-p_i/rho} expm1(-(f_i - p_i)/rho),
+// f_i - p_i when balanced (rho <= 0).  FP64 arithmetic, FP32 result; (g, q) give dS/d beta.
+__global__ __launch_bounds__(256) void k_grad_weights(const float *__restrict__ f,
+                                                      const float *__restrict__ p, int64_t n,
+                                                      double eps, double rho,
+                                                      float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double fi = f[i], pi = p[i];
+    const double v = rho > 0.0 ? -(rho + eps) * exp(-pi / rho) * expm1(-(fi - pi) / rho) : fi - pi;
+    out[i] = (float)v;
+}
+
+hipError_t launch_grad_weights(const float *f, const float *p, int64_t n, double eps, double rho,
+                               float *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, p, n,
+                       eps, rho, out);
+    return hipGetLastError();
+}
+
 }  // namespace skh

@@ -97,6 +97,8 @@ hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const
 hipError_t launch_grad_combine(const float *X, int n, int d, int kp, const float *P1,
                                const float *m1, const float *P2, const float *m2, float *grad,
                                hipStream_t s);
+hipError_t launch_grad_weights(const float *f, const float *p, int64_t n, double eps, double rho,
+                               float *out, hipStream_t s);
 
 // ---- K-means and the cluster-sorted, 32-padded layout (kmeans.hip) ----
 size_t kmeans_workspace_ints(int n, int k);

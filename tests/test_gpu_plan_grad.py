@@ -96,3 +96,87 @@ def test_grad_sum_is_mean_difference_and_autograd():
     ybar = (b[:, None].astype(np.float64) * y).sum(0)
     np.testing.assert_allclose(G.sum(0), xbar - ybar, atol=2e-4 * np.abs(xbar - ybar).max())
     assert S.dtype == torch.float64
+
+
+@pytest.mark.parametrize("reach", [None, 0.4])
+@pytest.mark.parametrize("n,m,d", [(500, 600, 3), (300, 250, 60), (1, 300, 3)])
+def test_all_gradients_match_oracle(n, m, d, reach):
+    # dS/da, dS/db (elementwise from the dual vectors), dS/dx and dS/dy (plan sums)
+    # against the oracle on the same FP32 inputs and potentials
+    import paper_2107_02010_amd as skh
+    if d == 3:
+        x, a = synth.blobs(n, seed=11), synth.random_weights(n, 12, zero_frac=0.1 if n > 1 else 0.0)
+        y, b = synth.blobs(m, seed=13), synth.random_weights(m, 14)
+        blur = 0.05
+    else:
+        x = synth.fibers(n, 5, spine_seed=6, seed=15)
+        y = synth.fibers(m, 5, spine_seed=6, seed=16)
+        a, b = synth.uniform_weights(n), synth.uniform_weights(m)
+        blur = 3.0
+    if reach is None:  # balanced needs equal masses
+        a = (a / a.astype(np.float64).sum()).astype(np.float32)
+        b = (b / b.astype(np.float64).sum()).astype(np.float32)
+    pot = _converged(x, a, y, b, blur, reach)
+    note(f"gradients n={n} m={m} d={d} reach={reach}")
+    G = skh.gradients(cuda(x), cuda(a), cuda(y), cuda(b), {k: cuda(v) for k, v in pot.items()},
+                      blur, reach)
+    G = {k: host(v) for k, v in G.items()}
+    ga = oracle.grad_weights(pot["f"], pot["p"], blur, reach)
+    gb = oracle.grad_weights(pot["g"], pot["q"], blur, reach)
+    # FP64 arithmetic on the device, one FP32 rounding
+    np.testing.assert_allclose(G["a"], ga, rtol=2 ** -23, atol=1e-37)
+    np.testing.assert_allclose(G["b"], gb, rtol=2 ** -23, atol=1e-37)
+    rx = oracle.grad_x(x, a, y, b, pot["f"], pot["g"], pot["p"], blur ** 2)
+    ry = oracle.grad_y(x, a, y, b, pot["f"], pot["g"], pot["q"], blur ** 2)
+    xs = np.abs(x).max() + np.abs(y).max()
+    assert np.all(np.abs(G["x"] - rx) <= 1e-4 * (a[:, None] * xs) + 1e-4 * np.abs(rx))
+    assert np.all(np.abs(G["y"] - ry) <= 1e-4 * (b[:, None] * xs) + 1e-4 * np.abs(ry))
+    # the x gradient of the combined entry is the one of grad_x
+    gx = host(skh.grad_x(cuda(x), cuda(a), cuda(y), cuda(b), cuda(pot["f"]), cuda(pot["g"]),
+                         cuda(pot["p"]), blur))
+    assert np.array_equal(gx, G["x"])
+
+
+def test_weight_gradient_dirac_through_the_solver():
+    # One Dirac each, unit masses: dS/da = dS/db = (eps + rho)(1 - e^{-C/(eps + 2 rho)})
+    # (derivative of the closed-form minimiser of eq. (2)), solver and kernel end to end
+    import paper_2107_02010_amd as skh
+    x, y = np.array([[0.3, -0.2]], np.float32), np.array([[-0.1, 0.4]], np.float32)
+    one = np.ones(1, np.float32)
+    blur, reach = 0.3, 0.5
+    eps, rho = blur ** 2, reach ** 2
+    C = 0.5 * float(((x.astype(np.float64) - y) ** 2).sum())
+    note("dirac weight gradient")
+    S, pot, st = skh.sinkhorn_divergence(cuda(x), cuda(one), cuda(y), cuda(one), blur=blur,
+                                         reach=reach, scaling=0.5, tol=1e-7, max_iters=2000,
+                                         check_every=1, potentials=True)
+    G = skh.gradients(cuda(x), cuda(one), cuda(y), cuda(one), pot, blur, reach, wrt=("a", "b"))
+    expect = (eps + rho) * (1 - np.exp(-C / (eps + 2 * rho)))
+    np.testing.assert_allclose(host(G["a"]), [expect], rtol=1e-5)
+    np.testing.assert_allclose(host(G["b"]), [expect], rtol=1e-5)
+
+
+@pytest.mark.parametrize("reach", [None, 0.4])
+def test_autograd_all_inputs(reach):
+    import torch
+
+    import paper_2107_02010_amd as skh
+    x, a, y, b = synth.blob_pair(800, seed=17)
+    kw = dict(blur=0.05, reach=reach, scaling=0.5, tol=1e-5, max_iters=3000, check_every=5)
+    X, A = cuda(x).requires_grad_(True), cuda(a).requires_grad_(True)
+    Y, B = cuda(y).requires_grad_(True), cuda(b).requires_grad_(True)
+    note(f"autograd all inputs reach={reach}")
+    S = skh.sinkhorn_loss(X, A, Y, B, **kw)
+    (2.0 * S).backward()
+    # the solver is deterministic: the same call yields the potentials the backward used
+    S2, pot, st = skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), potentials=True, **kw)
+    assert float(S.detach()) == S2
+    P = {k: host(v) for k, v in pot.items()}
+    np.testing.assert_allclose(host(A.grad), 2 * oracle.grad_weights(P["f"], P["p"], 0.05, reach),
+                               rtol=2 ** -22, atol=1e-37)
+    np.testing.assert_allclose(host(B.grad), 2 * oracle.grad_weights(P["g"], P["q"], 0.05, reach),
+                               rtol=2 ** -22, atol=1e-37)
+    G = skh.gradients(cuda(x), cuda(a), cuda(y), cuda(b), pot, 0.05, reach, wrt=("x", "y"))
+    assert np.array_equal(host(X.grad), 2 * host(G["x"]))
+    assert np.array_equal(host(Y.grad), 2 * host(G["y"]))
+    assert X.grad.dtype == torch.float32 and A.grad.dtype == torch.float32
