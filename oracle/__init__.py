@@ -240,6 +240,40 @@ def grad_weights(f, p, blur, reach=None):
     return out
 
 
+def flip_fibers(x, points):
+    """Mirror flips of fibres stored point-major (p0, p1, ..., p_{P-1}), each point d/P
+    coordinates: the same curve traversed backwards (Section 2: the tractograms are
+    augmented with the flips of all fibres, the simplest encoding of unoriented curves)."""
+    x = _pts(x)
+    n, d = x.shape
+    return x.reshape(n, points, d // points)[:, ::-1, :].reshape(n, d).copy()
+
+
+def label_transfer(x, a, y, b, labels, n_labels, blur, reach=None, flip_points=0, scaling=0.9,
+                   tol=0.0, max_iters=0, check_every=1, extra_iters=0):
+    """Soft labels of eq. (7) for the subject alpha from an atlas beta with integer labels
+    (Section 3, label transfer): the cross dual vectors (f, g) of OT(alpha, beta), then
+    Lab_i = sum_j beta_j onehot(l_j) exp((f_i + g_j - C_ij)/eps).  With flip_points = P
+    the subject is augmented with the flips of its fibres at the same weights and the two
+    versions of fibre i add up (the plan keeps the better-oriented one).  Returns
+    (Lab (n x L), score = sum_l Lab_il, the augmented loop's result dict)."""
+    x, y = _pts(x), _pts(y)
+    a, b = _f64(a), _f64(b)
+    n = x.shape[0]
+    if flip_points:
+        xs = np.concatenate([x, flip_fibers(x, flip_points)])
+        as_ = np.concatenate([a, a])
+    else:
+        xs, as_ = x, a
+    r = sinkhorn(xs, as_, y, b, blur, reach, scaling=scaling, tol=tol, max_iters=max_iters,
+                 check_every=check_every, extra_iters=extra_iters)
+    V = np.eye(int(n_labels))[np.asarray(labels, dtype=np.int64)]
+    lab = plan_apply(xs, as_, y, b, r["f"], r["g"], float(blur) ** 2, V, divide_by_a=True)
+    if flip_points:
+        lab = lab[:n] + lab[n:]
+    return lab, lab.sum(1), r
+
+
 def sinkhorn_divergence(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0,
                         tol=0.0, max_iters=0, check_every=1):
     """Run the loop and return (S by eq. (6), the loop's result dict)."""

@@ -14,6 +14,9 @@ the IFOF track-density maps).
 * ``density_maps``  track-density-like volumes: sums of Gaussian tubes along
                   jittered Bezier spines on a voxel grid, kept to the densest
                   voxels, returned as weighted voxel centres.
+* ``fiber_labels``, ``random_orientations``, ``outlier_fibers``  atlas labels
+                  (bundle ids), fibres stored in random directions, aberrant fibres
+                  far from every bundle (label-transfer inputs).
 * ``uniform_weights``  1/N weights.
 """
 from __future__ import annotations
@@ -108,6 +111,30 @@ def fibers(n: int, n_bundles: int, spine_seed: int, seed: int, points: int = 20,
         res = _resample_equal_arclength(poly, points)
         out[s:e] = (res.reshape(e - s, 3 * points) * scale).astype(np.float32)
     return out
+
+
+def fiber_labels(n: int, n_bundles: int) -> np.ndarray:
+    """Bundle index of each fibre of ``fibers(n, n_bundles, ...)`` (stored bundle after bundle)."""
+    sizes = [n // n_bundles + (1 if k < n % n_bundles else 0) for k in range(n_bundles)]
+    return np.repeat(np.arange(n_bundles, dtype=np.int32), sizes)
+
+
+def random_orientations(x: np.ndarray, points: int, seed: int, frac: float = 0.5) -> np.ndarray:
+    """Tractograms store each fibre in an arbitrary direction: a random fraction ``frac``
+    of the fibres (drawn from ``seed``) is stored with its points in reverse order."""
+    rng = np.random.default_rng(seed)
+    n, d = x.shape
+    rev = rng.uniform(size=n) < frac
+    out = x.copy()
+    out[rev] = x[rev].reshape(-1, points, d // points)[:, ::-1, :].reshape(-1, d)
+    return out
+
+
+def outlier_fibers(n: int, seed: int, points: int = 20, offset: float = 300.0) -> np.ndarray:
+    """Aberrant fibres: each along its own random spine, with every point moved by
+    ``offset`` mm along each axis, away from the bundles of ``fibers``."""
+    x = fibers(n, n, spine_seed=seed, seed=seed + 1, points=points)
+    return (x + np.float32(offset / np.sqrt(points))).astype(np.float32)
 
 
 def fiber_pair(n: int, n_bundles: int, seed: int, points: int = 20):

@@ -568,3 +568,68 @@ def test_self_and_cross_loops_are_independent(reach):
     np.testing.assert_array_equal(r1["p"], r3["p"])
     _, r4 = oracle.sinkhorn_divergence(y, b, y, b, **kw)
     np.testing.assert_array_equal(r1["q"], r4["q"])
+
+
+# ---------------------------------------------------------- label transfer ---
+
+def test_flip_fibers_reverses_points():
+    x = np.arange(18, dtype=np.float64).reshape(2, 9)  # 2 fibres of 3 points in 3-D
+    fx = oracle.flip_fibers(x, 3)
+    np.testing.assert_array_equal(fx[0], [6, 7, 8, 3, 4, 5, 0, 1, 2])
+    np.testing.assert_array_equal(oracle.flip_fibers(fx, 3), x)
+
+
+def _label_case(n_out=0, frac=0.5, points=4):
+    y = synth.fibers(60, 3, spine_seed=40, seed=41, points=points)
+    ly = synth.fiber_labels(60, 3)
+    x = synth.random_orientations(synth.fibers(45, 3, spine_seed=40, seed=42, points=points),
+                                  points, seed=43, frac=frac)
+    lx = synth.fiber_labels(45, 3)
+    if n_out:
+        x = np.concatenate([x, synth.outlier_fibers(n_out, seed=44, points=points)])
+        lx = np.concatenate([lx, -np.ones(n_out, np.int32)])
+    return x, _u(len(x)), y, _u(60), ly, lx
+
+
+@pytest.mark.parametrize("flips", [0, 4])
+def test_label_transfer_score_is_transported_mass(flips):
+    # At the fixed point the row marginal of the plan is alpha_i e^{-f_i/rho} (optimality of
+    # eq. (3) in f_i), so score_i = sum_l Lab_il = e^{-f_i/rho}, summed over both versions.
+    x, a, y, b, ly, lx = _label_case(n_out=5)
+    reach = 20.0
+    lab, score, r = oracle.label_transfer(x, a, y, b, ly, 3, 1.0, reach, flip_points=flips,
+                                          scaling=0.7, tol=1e-13, max_iters=50000)
+    assert r["converged"]
+    n = len(x)
+    e = np.exp(-r["f"] / reach ** 2)
+    np.testing.assert_allclose(score, e[:n] + e[n:] if flips else e, rtol=1e-8)
+    np.testing.assert_allclose(score, lab.sum(1), rtol=1e-12)
+
+
+def test_label_transfer_balanced_rows_on_simplex():
+    x, a, y, b, ly, lx = _label_case(frac=0.0)
+    lab, score, r = oracle.label_transfer(x, a, y, b, ly, 3, 1.0, None, scaling=0.7, tol=1e-13,
+                                          max_iters=50000)
+    assert r["converged"] and np.all(lab >= 0)
+    np.testing.assert_allclose(score, 1.0, rtol=1e-9)
+    assert np.all(np.argmax(lab, 1) == lx)
+
+
+def test_label_transfer_flips_and_outliers():
+    # Half the subject fibres are stored reversed, five are far from every bundle.  With the
+    # flips every inlier recovers its bundle and keeps about its mass; without them the
+    # reversed fibres (far from their bundle in that orientation) keep much less mass than
+    # any forward fibre; the aberrant fibres lose all of it either way.
+    x, a, y, b, ly, lx = _label_case(n_out=5)
+    ids = np.arange(180, dtype=np.float32).reshape(45, 4)  # which fibres were stored reversed
+    rev = synth.random_orientations(ids, 4, seed=43)[:, 0] != ids[:, 0]
+    inl = lx >= 0
+    lab, score, _ = oracle.label_transfer(x, a, y, b, ly, 3, 1.0, 20.0, flip_points=4,
+                                          scaling=0.7, tol=1e-10, max_iters=50000)
+    assert np.all(np.argmax(lab[inl], 1) == lx[inl])
+    assert np.all((score[inl] > 0.9) & (score[inl] < 1.5)) and np.all(score[~inl] < 1e-6)
+    lab0, score0, _ = oracle.label_transfer(x, a, y, b, ly, 3, 1.0, 20.0, scaling=0.7,
+                                            tol=1e-10, max_iters=50000)
+    assert rev.sum() > 10
+    assert score0[:45][rev].max() < 0.6 < 1.2 < score0[:45][~rev].min()
+    assert np.all(score0[~inl] < 1e-6)
