@@ -243,6 +243,32 @@ int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const
                   float *grad_b, float *grad_x, float *grad_y);
 
 /*
+ * Label transfer from a segmented atlas beta to a subject alpha (Section 3,
+ * label transfer; eq. (7)): the cross dual vectors (f, g) of OT_{eps,rho}(alpha,
+ * beta) from the symmetric loop, then soft labels
+ *   Lab_i = sum_j beta_j onehot(labels_j) exp((f_i + g_j - C_ij) / eps)  (eq. (7))
+ * and score_i = sum_l Lab_il, the fraction of alpha_i the plan transports: near 1
+ * for a matched fibre, near 0 for an outlier (unbalanced problems, reach > 0).
+ * flip_points = P > 0: the points are fibres of P points (d / P coordinates each,
+ * point-major); the subject is augmented with the mirror flip of every fibre at
+ * the same weight (Section 2, unoriented fibres), and the two versions of fibre
+ * i add up in Lab_i (the plan keeps the better-oriented one).  0: no flips.
+ * params: blur, reach, scaling, tolerance, multiscale settings as for
+ * skh_sinkhorn_divergence; init must be SKH_INIT_COLD, fixed 0 and labels_x/y
+ * NULL (the entry runs its own solve; a dense solve holds the unused self loops
+ * fixed).  labels: m ints in [0, L) (device), 1 <= L <= 64.  Outputs (device,
+ * caller order, each nullable but not both): lab (n x L), score (n).  stats as
+ * for skh_sinkhorn_divergence (of the augmented problem).
+ * Returns SKH_OK, SKH_NOT_CONVERGED (outputs valid), or an error: SKH_EINVAL for
+ * NULL inputs, labels out of range, flip_points not dividing d, 2 n beyond the
+ * point limit, or the parameter restrictions above.
+ */
+int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                       const float *b, int64_t m, int32_t d, const int32_t *labels, int32_t L,
+                       int32_t flip_points, const skh_params *params, float *lab, float *score,
+                       skh_stats *stats);
+
+/*
  * K-means coarse scale of one cloud (coarse-to-fine strategy, Section 2: a
  * K-means subsampling of the points for the first, coarse iterations).
  * Lloyd iterations from k evenly strided points (point floor(c n / k) for

@@ -19,6 +19,7 @@ from . import _lib
 from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT, SKH_FIX_P, SKH_FIX_Q, SKH_FIX_CROSS  # noqa: F401
 
 __all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "gradients",
+           "label_transfer",
            "diameter",
            "self_potential",
            "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
@@ -91,6 +92,28 @@ def softmin(x, y, w, h, eps: float, lam: float = 1.0, precision: str = "fp32") -
     return out
 
 
+def _solver_params(blur, reach, scaling, diameter, extra_iters, tol, max_iters, check_every,
+                   precision, timing, multiscale, jump_scale, trunc_theta, n_clusters,
+                   kmeans_iters):
+    P = _lib.default_params()
+    P.blur = float(blur)
+    P.reach = math.inf if reach is None else float(reach)
+    P.scaling = float(scaling)
+    P.diameter = 0.0 if diameter is None else float(diameter)
+    P.tol = float(tol)
+    P.extra_iters = int(extra_iters)
+    P.max_iters = int(max_iters)
+    P.check_every = int(check_every)
+    P.precision = _PREC[precision]
+    P.timing = 1 if timing else 0
+    P.multiscale = 1 if multiscale else 0
+    P.jump_scale = float(jump_scale)
+    P.trunc_theta = float(trunc_theta)
+    P.n_clusters = int(n_clusters)
+    P.kmeans_iters = int(kmeans_iters)
+    return P
+
+
 def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: float = 0.9,
                         diameter=None, extra_iters: int = 0, tol: float = 0.0,
                         max_iters: int = 1000, check_every: int = 5, precision: str = "fp32",
@@ -120,22 +143,9 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     n, m, d = x.shape[0], y.shape[0], x.shape[1]
     a = _as_vec(a, n, "a", x.device)
     b = _as_vec(b, m, "b", x.device)
-    P = _lib.default_params()
-    P.blur = float(blur)
-    P.reach = math.inf if reach is None else float(reach)
-    P.scaling = float(scaling)
-    P.diameter = 0.0 if diameter is None else float(diameter)
-    P.tol = float(tol)
-    P.extra_iters = int(extra_iters)
-    P.max_iters = int(max_iters)
-    P.check_every = int(check_every)
-    P.precision = _PREC[precision]
-    P.timing = 1 if timing else 0
-    P.multiscale = 1 if multiscale else 0
-    P.jump_scale = float(jump_scale)
-    P.trunc_theta = float(trunc_theta)
-    P.n_clusters = int(n_clusters)
-    P.kmeans_iters = int(kmeans_iters)
+    P = _solver_params(blur, reach, scaling, diameter, extra_iters, tol, max_iters, check_every,
+                       precision, timing, multiscale, jump_scale, trunc_theta, n_clusters,
+                       kmeans_iters)
     P.fixed = int(fixed)
     if labels is not None:
         lx, ly = labels
@@ -168,6 +178,39 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     if potentials:
         return S.value, dict(f=f, g=g, p=p, q=q), st.as_dict()
     return S.value
+
+
+def label_transfer(x, a, y, b, labels, n_labels: int, blur: float = 1.0, reach=20.0,
+                   flip_points: int = 0, scaling: float = 0.9, diameter=None,
+                   extra_iters: int = 0, tol: float = 1e-4, max_iters: int = 1000,
+                   check_every: int = 5, precision: str = "fp32", multiscale: bool = False,
+                   jump_scale: float = 0.0, trunc_theta: float = 20.0, n_clusters: int = 0,
+                   kmeans_iters: int = 10, stats: bool = False):
+    """Soft labels of eq. (7) for the subject (x, a) from an atlas (y, b) with int32 labels in
+    [0, n_labels) (Section 3, label transfer).  flip_points = P augments the subject with the
+    mirror flips of its P-point fibres (the two versions add up).  Returns (Lab (n, L),
+    score (n)); score ~ 1 for a matched fibre, ~ 0 for an outlier (unbalanced)."""
+    x, y = _as_points(x, "x"), _as_points(y, "y")
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same dimension")
+    n, m, d = x.shape[0], y.shape[0], x.shape[1]
+    a, b = _as_vec(a, n, "a", x.device), _as_vec(b, m, "b", x.device)
+    if not (isinstance(labels, torch.Tensor) and labels.is_cuda and labels.dtype == torch.int32
+            and labels.is_contiguous() and labels.numel() == m):
+        raise ValueError(f"labels must be a contiguous int32 CUDA tensor of {m} values")
+    P = _solver_params(blur, reach, scaling, diameter, extra_iters, tol, max_iters, check_every,
+                       precision, False, multiscale, jump_scale, trunc_theta, n_clusters,
+                       kmeans_iters)
+    L = int(n_labels)
+    lab = torch.empty((n, L), dtype=torch.float32, device=x.device)
+    score = torch.empty(n, dtype=torch.float32, device=x.device)
+    st = _lib.SkhStats()
+    ctx = _Ctx.get(x.device)
+    rc = _lib.load().skh_label_transfer(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d,
+                                        _ptr(labels), L, int(flip_points), ctypes.byref(P),
+                                        _ptr(lab), _ptr(score), ctypes.byref(st))
+    _lib.check(rc, ctx, allow_not_converged=True)
+    return (lab, score, st.as_dict()) if stats else (lab, score)
 
 
 def diameter(x, y) -> float:

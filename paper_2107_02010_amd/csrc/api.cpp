@@ -155,7 +155,7 @@ void skh_destroy(skh_ctx *ctx) {
     {
         DeviceGuard guard(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 4; ++k)
             if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
         if (ctx->host) (void)hipHostFree(ctx->host);
         for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -1050,6 +1050,76 @@ int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const
         if (rc) return rc;
     }
     return SKH_OK;
+}
+
+int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                       const float *b, int64_t m, int32_t d, const int32_t *labels, int32_t L,
+                       int32_t flip_points, const skh_params *params, float *lab, float *score,
+                       skh_stats *stats) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x || !a || !y || !b || !labels || !params) return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (!lab && !score) return fail(ctx, SKH_EINVAL, "lab and score are both NULL");
+    if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
+        return fail(ctx, SKH_EINVAL, "n, m out of range");
+    if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
+    if (L < 1 || L > 64) return fail(ctx, SKH_EINVAL, "L must be in [1, 64]");
+    if (flip_points < 0 || (flip_points > 0 && d % flip_points != 0))
+        return fail(ctx, SKH_EINVAL, "flip_points must be 0 or divide d");
+    const int64_t na = flip_points ? 2 * n : n;
+    if (na > kMaxPoints) return fail(ctx, SKH_EINVAL, "2 n exceeds the point limit");
+    if (params->init != SKH_INIT_COLD || params->fixed || params->labels_x || params->labels_y)
+        return fail(ctx, SKH_EINVAL,
+                    "label transfer runs its own cold solve (init, fixed, labels_x/y unset)");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = ctx->stream;
+    float *xa = nullptr, *aa = nullptr, *f, *g, *p, *q, *V, *aug;
+    int *bad;
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c(pass ? ctx->ws[3] : nullptr);
+        if (flip_points) {
+            xa = c.take<float>((size_t)na * d);
+            aa = c.take<float>(na);
+        }
+        f = c.take<float>(na);
+        p = c.take<float>(na);
+        g = c.take<float>(m);
+        q = c.take<float>(m);
+        V = c.take<float>((size_t)m * L);
+        aug = c.take<float>((size_t)na * L);
+        bad = c.take<int>(1);
+        if (!pass) {
+            int rc = ensure_ws(ctx, 3, c.off);
+            if (rc) return rc;
+        }
+    }
+    char *hb = static_cast<char *>(ctx->host);
+    SKH_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    SKH_HIP(skh::launch_check_labels(labels, (int)m, L, bad, s));
+    SKH_HIP(hipMemcpyAsync(hb + 3072, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    SKH_HIP(hipStreamSynchronize(s));
+    if (*reinterpret_cast<const int *>(hb + 3072))
+        return fail(ctx, SKH_EINVAL, "atlas label out of range [0, L)");
+    if (flip_points) SKH_HIP(skh::launch_flip_augment(x, a, n, d, flip_points, xa, aa, s));
+    const float *X = flip_points ? xa : x, *A = flip_points ? aa : a;
+    // only the cross loop is needed: the dense solve holds the self loops fixed at zero
+    skh_params P = *params;
+    if (!P.multiscale) {
+        P.fixed = SKH_FIX_P | SKH_FIX_Q;
+        P.init = SKH_INIT_GIVEN;
+        SKH_HIP(hipMemsetAsync(f, 0, sizeof(float) * na, s));
+        SKH_HIP(hipMemsetAsync(p, 0, sizeof(float) * na, s));
+        SKH_HIP(hipMemsetAsync(g, 0, sizeof(float) * m, s));
+        SKH_HIP(hipMemsetAsync(q, 0, sizeof(float) * m, s));
+    }
+    double S = 0.0;
+    const int rc = skh_sinkhorn_divergence(ctx, X, A, na, y, b, m, d, &P, &S, f, g, p, q, stats);
+    if (rc < 0) return rc;
+    SKH_HIP(skh::launch_one_hot(labels, m, L, V, s));
+    const int rc2 = skh_plan_apply(ctx, X, A, na, y, b, m, d, f, g, P.blur * P.blur, V, L, 1, aug,
+                                   nullptr);
+    if (rc2) return rc2;
+    SKH_HIP(skh::launch_label_fold(aug, n, L, flip_points ? 1 : 0, lab, score, s));
+    return rc;
 }
 
 int skh_diameter(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,

@@ -14,8 +14,9 @@
 struct skh_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    void *ws[3] = {nullptr, nullptr, nullptr};  // setup, loop, warm-start network buffers
-    size_t ws_bytes[3] = {0, 0, 0};
+    // setup, loop, warm-start network, label-transfer buffers
+    void *ws[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t ws_bytes[4] = {0, 0, 0, 0};
     void *host = nullptr;  // pinned, kHostBytes
     int num_cus = 256;
     std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches

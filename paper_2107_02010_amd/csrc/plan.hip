@@ -304,4 +304,77 @@ hipError_t launch_grad_weights(const float *f, const float *p, int64_t n, double
     return hipGetLastError();
 }
 
+// Label transfer (Section 3): the subject augmented with the mirror flips of its fibres
+// (Section 2: tractograms are augmented with the flips of all fibres, the simplest
+// encoding of unoriented curves).  Rows [0, n) copy x; row n + i is fibre i with its P
+// points in reverse order (each point d / P coordinates); the weights are repeated.
+__global__ __launch_bounds__(256) void k_flip_augment(const float *__restrict__ x,
+                                                      const float *__restrict__ a, int64_t n,
+                                                      int d, int P, float *__restrict__ xa,
+                                                      float *__restrict__ aa) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t i = e / d;
+    const int t = (int)(e - i * d);
+    const int D0 = d / P;
+    const int pt = t / D0, c = t - pt * D0;
+    const float v = x[e];
+    xa[e] = v;
+    xa[(n + i) * d + (int64_t)(P - 1 - pt) * D0 + c] = v;
+    if (t == 0) {
+        aa[i] = a[i];
+        aa[n + i] = a[i];
+    }
+}
+
+// One-hot atlas labels: V[j][l] = 1 if labels[j] == l (m x L, labels checked beforehand).
+__global__ __launch_bounds__(256) void k_one_hot(const int *__restrict__ labels, int64_t m, int L,
+                                                 float *__restrict__ V) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= m * L) return;
+    const int64_t j = e / L;
+    V[e] = labels[j] == (int)(e - j * L) ? 1.0f : 0.0f;
+}
+
+// Soft labels of eq. (7) per subject fibre: with flips the two versions add up (the plan
+// keeps mass on the better-oriented one); score_i = sum_l Lab_il (FP64 sum), the fraction
+// of the fibre's weight the plan transports (close to 0 for an outlier).
+__global__ __launch_bounds__(256) void k_label_fold(const float *__restrict__ aug, int64_t n,
+                                                    int L, int flips, float *__restrict__ lab,
+                                                    float *__restrict__ score) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) {
+        float v = aug[i * L + l];
+        if (flips) v += aug[(n + i) * L + l];
+        if (lab) lab[i * L + l] = v;
+        s += (double)v;
+    }
+    if (score) score[i] = (float)s;
+}
+
+hipError_t launch_flip_augment(const float *x, const float *a, int64_t n, int d, int P, float *xa,
+                               float *aa, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flip_augment, dim3((unsigned)((n * d + 255) / 256)), dim3(256), 0, s, x, a,
+                       n, d, P, xa, aa);
+    return hipGetLastError();
+}
+
+hipError_t launch_one_hot(const int *labels, int64_t m, int L, float *V, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_one_hot, dim3((unsigned)((m * L + 255) / 256)), dim3(256), 0, s, labels, m,
+                       L, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_fold(const float *aug, int64_t n, int L, int flips, float *lab, float *score,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_label_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, aug, n, L,
+                       flips, lab, score);
+    return hipGetLastError();
+}
+
 }  // namespace skh

@@ -99,6 +99,11 @@ hipError_t launch_grad_combine(const float *X, int n, int d, int kp, const float
                                hipStream_t s);
 hipError_t launch_grad_weights(const float *f, const float *p, int64_t n, double eps, double rho,
                                float *out, hipStream_t s);
+hipError_t launch_flip_augment(const float *x, const float *a, int64_t n, int d, int P, float *xa,
+                               float *aa, hipStream_t s);
+hipError_t launch_one_hot(const int *labels, int64_t m, int L, float *V, hipStream_t s);
+hipError_t launch_label_fold(const float *aug, int64_t n, int L, int flips, float *lab, float *score,
+                             hipStream_t s);
 
 // ---- K-means and the cluster-sorted, 32-padded layout (kmeans.hip) ----
 size_t kmeans_workspace_ints(int n, int k);

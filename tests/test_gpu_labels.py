@@ -1,0 +1,92 @@
+"""GPU parity of the label transfer (eq. (7), Section 3) with mirror-flip augmentation
+and outlier scores, against the FP64 oracle run the same number of iterations."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import cuda, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, m, bundles, n_out, points, seed):
+    y = synth.fibers(m, bundles, spine_seed=seed, seed=seed + 1, points=points)
+    ly = synth.fiber_labels(m, bundles)
+    x = synth.random_orientations(synth.fibers(n, bundles, spine_seed=seed, seed=seed + 2,
+                                               points=points), points, seed=seed + 3)
+    lx = synth.fiber_labels(n, bundles)
+    if n_out:
+        x = np.concatenate([x, synth.outlier_fibers(n_out, seed=seed + 4, points=points)])
+        lx = np.concatenate([lx, -np.ones(n_out, np.int32)])
+    return x, synth.uniform_weights(len(x)), y, synth.uniform_weights(m), ly, lx
+
+
+def _labels(ly):
+    import torch
+    return torch.as_tensor(ly, dtype=torch.int32).cuda()
+
+
+@pytest.mark.parametrize("flips", [0, 4])
+@pytest.mark.parametrize("n,m,bundles,n_out", [(300, 400, 3, 10), (97, 130, 5, 3)])
+def test_label_transfer_matches_oracle(n, m, bundles, n_out, flips):
+    import paper_2107_02010_amd as skh
+    x, a, y, b, ly, lx = _case(n, m, bundles, n_out, 4, seed=50 + n)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.7, extra_iters=30)
+    note(f"label transfer n={len(x)} m={m} L={bundles} flips={flips}")
+    lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), bundles,
+                                    flip_points=flips, tol=0.0, **kw)
+    lab, score = host(lab), host(score)
+    ref, rscore, r = oracle.label_transfer(x, a, y, b, ly, bundles, flip_points=flips, **kw)
+    # Lab_i carries exp((f_i + g_j)/eps): each iteration of the FP32 loop leaves a few ulps
+    # of rounding in f and g (at most 4 per iteration, carried through the averaging), so
+    # row i is off by up to 4 k ulps of (|f_i| + max|g|) over eps after k iterations
+    fi = np.abs(r["f"][:len(x)])
+    if flips:
+        fi = np.maximum(fi, np.abs(r["f"][len(x):]))
+    rel = 4 * r["iters"] * 2.0 ** -24 * (fi + np.abs(r["g"]).max()) / kw["blur"] ** 2
+    err = np.abs(lab - ref) / (rel[:, None] * rscore[:, None] + 1e-30)
+    assert np.all(err <= 1.0), (rel.max(), err.max())
+    assert np.all(np.abs(score - rscore) <= rel * rscore + 1e-30)
+    np.testing.assert_allclose(score, lab.sum(1), rtol=1e-5, atol=1e-30)
+    # the decided labels agree wherever the oracle's margin is clear (rows that carry mass:
+    # an outlier's labels, ~1e-140, are below the FP32 range)
+    top2 = np.sort(ref, 1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0] > 1e-2 * rscore) & (rscore > 1e-20)
+    assert clear.sum() >= 0.9 * n
+    assert np.array_equal(np.argmax(lab, 1)[clear], np.argmax(ref, 1)[clear])
+
+
+def test_label_transfer_multiscale_fibres():
+    # 20k-fibre atlas of 10 bundles, 60-D fibres; the subject's fibres stored in random
+    # directions plus 1 % aberrant fibres; multiscale solve to the usual tolerance
+    import paper_2107_02010_amd as skh
+    x, a, y, b, ly, lx = _case(20000, 20000, 10, 200, 20, seed=60)
+    note("label transfer multiscale 20k flips")
+    lab, score, st = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 10,
+                                        flip_points=20, multiscale=True, tol=1e-4, stats=True)
+    lab, score = host(lab), host(score)
+    inl = lx >= 0
+    assert st["iters"] > 0
+    assert np.mean(np.argmax(lab[inl], 1) == lx[inl]) > 0.999
+    assert np.all(score[~inl] < 1e-3)
+    assert np.all(score[inl] > 0.5)
+
+
+def test_label_transfer_rejects_bad_arguments():
+    import torch
+
+    import paper_2107_02010_amd as skh
+    x, a, y, b, ly, lx = _case(50, 60, 3, 0, 4, seed=70)
+    note("label transfer argument checks")
+    bad = ly.copy()
+    bad[7] = 3
+    with pytest.raises(skh.SkhError):
+        skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(bad), 3)
+    with pytest.raises(skh.SkhError):  # 12 coordinates are not fibres of 5 points
+        skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 3, flip_points=5)
+    with pytest.raises(ValueError):
+        skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b),
+                           torch.as_tensor(ly, dtype=torch.int64).cuda(), 3)
+    lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 3)
+    assert torch.isfinite(lab).all() and torch.isfinite(score).all()
