@@ -19,6 +19,11 @@ path, BF16 split + learned warm start (network trained by ws_train, loaded from
 paper_2107_02010_amd/data/ws_fibers.safetensors; tokens, network forward and the
 broadcast are inside the timed region).
 
+--workload grad200k: all four gradients of S from the dual vectors of a converged
+200k x 200k fibre solve (reach 20 mm); Gpair/s of the plan-weighted kernels.
+--workload labels200k: label transfer from a 200k-fibre labelled atlas to a 200k-fibre
+subject (random fibre directions, 1 % aberrant fibres) with flip augmentation.
+
 Prints one JSON line:
   value       = softmin point pairs evaluated / wall time of the timed steps (Gpair/s)
   roofline    = the softmin kernel's algorithmic MFMA flops per launch over its
@@ -189,13 +194,102 @@ def bench_multiscale(args, skh, synth):
     return 0
 
 
+def _timed(fn, steps, warmup):
+    """Mean wall time of fn() over `steps` calls after `warmup`, bracketed by synchronisations."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def bench_gradients(args, skh, synth):
+    """All four gradients of S (dS/dx, dS/dy by the plan-weighted kernels, dS/da, dS/db
+    elementwise) from the dual vectors of a converged 200k x 200k fibre solve."""
+    import torch
+    n = args.n
+    print(f"[bench] generating {n} x {n} fibre clouds", file=sys.stderr, flush=True)
+    x, a, y, b = synth.fiber_pair(n, args.bundles, seed=0)
+    X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+    S, pot, st = skh.sinkhorn_divergence(X, A, Y, B, blur=1.0, reach=20.0, scaling=0.9,
+                                         tol=1e-4, max_iters=5000, precision="bf16x3",
+                                         potentials=True)
+    print("[bench] solve done; timing the gradients", file=sys.stderr, flush=True)
+    dt, G = _timed(lambda: skh.gradients(X, A, Y, B, pot, 1.0, 20.0), args.steps, args.warmup)
+    pairs = 2.0 * n * n + 2.0 * n * n  # grad_x: n x m and n x n plans; grad_y: m x n, m x m
+    flop = 256  # per pair: 64-wide FP32 contraction + 64-wide weighted coordinate sum (MFMA)
+    ach = flop * pairs / dt / 1e12
+    out = {"metric": f"Gpair/s of the gradient plan kernels (dS/dx, dS/dy, dS/da, dS/db; "
+                     f"{n} x {n} 60-D fibres)",
+           "value": round(pairs / dt / 1e9, 3), "unit": "Gpair/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"gradients after a converged solve, fibre clouds n=m={n}, "
+                                  f"{args.bundles} bundles, blur 1 mm, reach 20 mm"},
+           "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": 157.3,
+                        "unit": "TFLOP/s", "frac": round(ach / 157.3, 4), "traffic": None,
+                        "flop_per_pair": flop, "timed": "whole skh_gradients call"},
+           "grad_norms": {k: float(torch.linalg.vector_norm(v.double())) for k, v in G.items()}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_labels(args, skh, synth):
+    """Label transfer (eq. (7)) from a 200k-fibre atlas of 50 labelled bundles to a 200k-fibre
+    subject stored in random directions plus 1 % aberrant fibres, with flip augmentation,
+    multiscale BF16 solve over the Algorithm's schedule."""
+    import numpy as np
+    import torch
+    n = args.n
+    nout = n // 100
+    print(f"[bench] generating atlas and subject ({n} fibres, {nout} outliers)", file=sys.stderr,
+          flush=True)
+    y = synth.fibers(n, args.bundles, spine_seed=0, seed=1)
+    ly = synth.fiber_labels(n, args.bundles)
+    x = np.concatenate([synth.random_orientations(synth.fibers(n, args.bundles, spine_seed=0,
+                                                               seed=2), 20, seed=3),
+                        synth.outlier_fibers(nout, seed=4)])
+    lx = np.concatenate([synth.fiber_labels(n, args.bundles), -np.ones(nout, np.int32)])
+    a, b = synth.uniform_weights(len(x)), synth.uniform_weights(n)
+    X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+    LY = torch.as_tensor(ly, dtype=torch.int32).cuda()
+    kw = dict(blur=1.0, reach=20.0, flip_points=20, multiscale=True, tol=0.0,
+              precision="bf16x3", stats=True)
+    dt, (lab, score, st) = _timed(lambda: skh.label_transfer(X, A, Y, B, LY, args.bundles, **kw),
+                                  args.steps, args.warmup)
+    lab, score = lab.cpu().numpy(), score.cpu().numpy()
+    inl = lx >= 0
+    out = {"metric": f"time to soft labels, {n}-fibre subject (+1 % outliers, flips) from a "
+                     f"{n}-fibre atlas",
+           "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+           "config": {"workload": f"label transfer, {args.bundles} labelled bundles, 60-D fibres "
+                                  "stored in random directions, flip augmentation, blur 1 mm, "
+                                  "reach 20 mm, scaling 0.9, multiscale, the Algorithm's "
+                                  "schedule (one iteration per scale)"},
+           "accuracy_inliers": float(np.mean(np.argmax(lab[inl], 1) == lx[inl])),
+           "max_outlier_score": float(score[~inl].max()),
+           "min_inlier_score": float(score[inl].min()),
+           "iters": st["iters"], "converged": st["converged"],
+           "kept_fraction": round(st["pairs"] / max(st["dense_pairs"], 1.0), 5)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
-    ap.add_argument("--workload", default="fibers200k", choices=["fibers200k", "multiscale1m"])
+    ap.add_argument("--workload", default="fibers200k",
+                    choices=["fibers200k", "multiscale1m", "grad200k", "labels200k"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison solve")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
@@ -227,6 +321,10 @@ def main() -> int:
 
     if args.workload == "multiscale1m":
         return bench_multiscale(args, skh, synth)
+    if args.workload == "grad200k":
+        return bench_gradients(args, skh, synth)
+    if args.workload == "labels200k":
+        return bench_labels(args, skh, synth)
     print(f"[bench] generating {args.n} x {args.n} fibre clouds", file=sys.stderr, flush=True)
     x, a, y, b = synth.fiber_pair(args.n, args.bundles, seed=0)
     dev = torch.device("cuda:0")

@@ -182,14 +182,18 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
 
 def label_transfer(x, a, y, b, labels, n_labels: int, blur: float = 1.0, reach=20.0,
                    flip_points: int = 0, scaling: float = 0.9, diameter=None,
-                   extra_iters: int = 0, tol: float = 1e-4, max_iters: int = 1000,
+                   extra_iters: int = 0, tol: float = 0.0, max_iters: int = 1000,
                    check_every: int = 5, precision: str = "fp32", multiscale: bool = False,
                    jump_scale: float = 0.0, trunc_theta: float = 20.0, n_clusters: int = 0,
                    kmeans_iters: int = 10, stats: bool = False):
     """Soft labels of eq. (7) for the subject (x, a) from an atlas (y, b) with int32 labels in
     [0, n_labels) (Section 3, label transfer).  flip_points = P augments the subject with the
     mirror flips of its P-point fibres (the two versions add up).  Returns (Lab (n, L),
-    score (n)); score ~ 1 for a matched fibre, ~ 0 for an outlier (unbalanced)."""
+    score (n)); score ~ 1 for a matched fibre, ~ 0 for an outlier (unbalanced).  The
+    default runs the Algorithm's schedule (one iteration per scale, tol = 0); with flips
+    the subject carries twice the atlas mass, and the unbalanced loop removes the excess
+    only at the rate rho / (rho + eps) per iteration, so tight tolerances take thousands
+    of iterations without changing the decided labels."""
     x, y = _as_points(x, "x"), _as_points(y, "y")
     if x.shape[1] != y.shape[1]:
         raise ValueError("x and y must have the same dimension")

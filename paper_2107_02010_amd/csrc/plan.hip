@@ -31,7 +31,11 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
     constexpr int H = KP / 2;
     constexpr int STRIDE = KP + 4;
     constexpr int V4 = KP / 4;
-    constexpr int VSTRIDE = LP + 4;
+    // value rows: the matrix-core path reads one float per lane from rows 4 apart in the
+    // two lane halves, so the stride keeps those 32 words apart in the banks
+    constexpr int VSTRIDE = LP >= 32 ? LP + 8 : LP + 4;
+    constexpr bool kMfmaValues = LP >= 32;
+    constexpr int NT2 = kMfmaValues ? LP / 32 : 1;  // 32-wide value tiles
     __shared__ __attribute__((aligned(16))) float tile[kColsPerTile * STRIDE];
     __shared__ __attribute__((aligned(16))) float vtile[kColsPerTile * VSTRIDE];
 
@@ -70,9 +74,14 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
     const int c_begin = chunk * chunk_cols;
     const int c_end = min(n_cols, c_begin + chunk_cols);
     float m = ninf(), wsum = 0.0f;
-    float vacc[LP];
+    float vacc[kMfmaValues ? 1 : LP];
 #pragma unroll
-    for (int l = 0; l < LP; ++l) vacc[l] = 0.0f;
+    for (int l = 0; l < (kMfmaValues ? 1 : LP); ++l) vacc[l] = 0.0f;
+    v16f pacc[NT2];
+#pragma unroll
+    for (int t = 0; t < NT2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) pacc[t][r] = 0.0f;
 
     for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
         __syncthreads();
@@ -107,51 +116,103 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
             float tmax = acc[0];
 #pragma unroll
             for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
-            const float mn = fmaxf(m, tmax);
-            if (mn > ninf()) {
-                const float sc = fast_exp2(m - mn);
-                wsum *= sc;
+            if constexpr (kMfmaValues) {
+                // One level per row: both lane halves feed the same K-reduction below.
+                // Register r of lane (row li, half h) holds the weight of column
+                // c_r(h) = 8 (r / 4) + 4 h + r % 4, which is exactly the B operand
+                // (K index h, column li) of a v_mfma_f32_32x32x2f32 summing over the
+                // column pair {c_r(0), c_r(1)}; A is V at those columns for 32 values.
+                // The products run with every lane active (no branch around them): a
+                // block of masked columns (u_j = -inf, the same for every row) uses
+                // base 0, so its weights are exactly 0.
+                tmax = fmaxf(tmax, __shfl_xor(tmax, 32, 64));
+                const float mn = fmaxf(m, tmax);
+                if (mn > m) {
+                    const float sc = fast_exp2(m - mn);  // 0 while m = -inf
+                    wsum *= sc;
 #pragma unroll
-                for (int l = 0; l < LP; ++l) vacc[l] *= sc;
+                    for (int t = 0; t < NT2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) pacc[t][r] *= sc;
+                    m = mn;
+                }
+                const float base = m > ninf() ? m : 0.0f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float w = fast_exp2(acc[r] - mn);
+                    const float w = fast_exp2(acc[r] - base);
                     wsum += w;
                     const int jl = jb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                    const float *vr = &vtile[jl * VSTRIDE];
 #pragma unroll
-                    for (int l = 0; l < LP; l += 4) {
-                        const float4 vv = *reinterpret_cast<const float4 *>(vr + l);
-                        vacc[l] = fmaf(w, vv.x, vacc[l]);
-                        if (l + 1 < LP) vacc[l + 1] = fmaf(w, vv.y, vacc[l + 1]);
-                        if (l + 2 < LP) vacc[l + 2] = fmaf(w, vv.z, vacc[l + 2]);
-                        if (l + 3 < LP) vacc[l + 3] = fmaf(w, vv.w, vacc[l + 3]);
-                    }
+                    for (int t = 0; t < NT2; ++t)
+                        pacc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            vtile[jl * VSTRIDE + 32 * t + li], w, pacc[t], 0, 0, 0);
                 }
-                m = mn;
+            } else {
+                const float mn = fmaxf(m, tmax);
+                if (mn > ninf()) {
+                    const float sc = fast_exp2(m - mn);
+                    wsum *= sc;
+#pragma unroll
+                    for (int l = 0; l < LP; ++l) vacc[l] *= sc;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float w = fast_exp2(acc[r] - mn);
+                        wsum += w;
+                        const int jl = jb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                        const float *vr = &vtile[jl * VSTRIDE];
+#pragma unroll
+                        for (int l = 0; l < LP; l += 4) {
+                            const float4 vv = *reinterpret_cast<const float4 *>(vr + l);
+                            vacc[l] = fmaf(w, vv.x, vacc[l]);
+                            if (l + 1 < LP) vacc[l + 1] = fmaf(w, vv.y, vacc[l + 1]);
+                            if (l + 2 < LP) vacc[l + 2] = fmaf(w, vv.z, vacc[l + 2]);
+                            if (l + 3 < LP) vacc[l + 3] = fmaf(w, vv.w, vacc[l + 3]);
+                        }
+                    }
+                    m = mn;
+                }
             }
         }
     }
 
-    // merge the two lane halves of each row
-    const float m2 = __shfl_xor(m, 32, 64);
-    const float M = fmaxf(m, m2);
-    const float s1 = M > ninf() ? fast_exp2(m - M) : 0.0f;
-    const float s2 = M > ninf() ? fast_exp2(m2 - M) : 0.0f;
-    const float w2 = __shfl_xor(wsum, 32, 64);
-    const float W = wsum * s1 + w2 * s2;
-    // partial record: [M, W, P_0 .. P_{L-1}]
     const int RW = L + 2;
     float *rec = part + ((size_t)chunk * n_rows + i) * RW;
+    if constexpr (kMfmaValues) {
+        // the level is row-uniform and each value sum is complete in one lane:
+        // lane (li, h) holds values 32 t + 8 (r / 4) + 4 h + r % 4 of row li
+        const float W = wsum + __shfl_xor(wsum, 32, 64);
+        if (i < n_rows) {
 #pragma unroll
-    for (int l = 0; l < LP; ++l) {
-        const float o = __shfl_xor(vacc[l], 32, 64);
-        const float val = vacc[l] * s1 + o * s2;
-        if (h == 0 && i < n_rows && l < L) rec[2 + l] = val;
-    }
-    if (h == 0 && i < n_rows) {
-        rec[0] = M;
-        rec[1] = W;
+            for (int t = 0; t < NT2; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int l = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (l < L) rec[2 + l] = pacc[t][r];
+                }
+            if (h == 0) {
+                rec[0] = m;
+                rec[1] = W;
+            }
+        }
+    } else {
+        // merge the two lane halves of each row
+        const float m2 = __shfl_xor(m, 32, 64);
+        const float M = fmaxf(m, m2);
+        const float s1 = M > ninf() ? fast_exp2(m - M) : 0.0f;
+        const float s2 = M > ninf() ? fast_exp2(m2 - M) : 0.0f;
+        const float w2 = __shfl_xor(wsum, 32, 64);
+        const float W = wsum * s1 + w2 * s2;
+        // partial record: [M, W, P_0 .. P_{L-1}]
+#pragma unroll
+        for (int l = 0; l < LP; ++l) {
+            const float o = __shfl_xor(vacc[l], 32, 64);
+            const float val = vacc[l] * s1 + o * s2;
+            if (h == 0 && i < n_rows && l < L) rec[2 + l] = val;
+        }
+        if (h == 0 && i < n_rows) {
+            rec[0] = M;
+            rec[1] = W;
+        }
     }
 }
 
