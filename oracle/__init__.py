@@ -75,6 +75,17 @@ def _load():
             lib.oracle_grad_x.restype = None
             lib.oracle_grad_weights.argtypes = [_I64, _P, _P, _D, _D, _P]
             lib.oracle_grad_weights.restype = None
+            lib.oracle_softmin_p.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _D, _P]
+            lib.oracle_softmin_p.restype = None
+            lib.oracle_sinkhorn_p.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _D, _D,
+                                              _I, _D, _I, _I, _I, _D, _P, _P, _P, _P, _P]
+            lib.oracle_sinkhorn_p.restype = _I
+            lib.oracle_divergence_p.argtypes = [_I64, _I64, _P, _P, _P, _P, _P, _P, _D, _D, _D]
+            lib.oracle_divergence_p.restype = _D
+            lib.oracle_ot_dual_p.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _D, _D]
+            lib.oracle_ot_dual_p.restype = _D
+            lib.oracle_ot_primal_p.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _P, _P, _D, _D, _D]
+            lib.oracle_ot_primal_p.restype = _D
             _lib = lib
     return _lib
 
@@ -108,13 +119,14 @@ def num_threads() -> int:
     return int(_load().oracle_num_threads())
 
 
-def softmin(rows, cols, w, h, eps, lam=1.0):
-    """out_i = -lam*eps*log sum_j w_j exp((h_j - C(rows_i, cols_j))/eps)  (Algorithm, tilde updates)."""
+def softmin(rows, cols, w, h, eps, lam=1.0, p=2.0):
+    """out_i = -lam*eps*log sum_j w_j exp((h_j - C(rows_i, cols_j))/eps)  (Algorithm, tilde updates),
+    C = |x - y|^p / p."""
     r, c = _pts(rows), _pts(cols)
     w, h = _f64(w), _f64(h)
     out = np.empty(r.shape[0])
-    _load().oracle_softmin(r.shape[0], c.shape[0], r.shape[1], _ptr(r), _ptr(c), _ptr(w),
-                           _ptr(h), float(eps), float(lam), _ptr(out))
+    _load().oracle_softmin_p(r.shape[0], c.shape[0], r.shape[1], _ptr(r), _ptr(c), _ptr(w),
+                             _ptr(h), float(eps), float(lam), float(p), _ptr(out))
     return out
 
 
@@ -134,11 +146,13 @@ def schedule(diam, blur, scaling):
 
 
 def sinkhorn(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0, tol=0.0,
-             max_iters=0, check_every=1, init=None):
-    """Symmetric averaged Sinkhorn loop with eps-scaling (Algorithm).
+             max_iters=0, check_every=1, init=None, p=2.0):
+    """Symmetric averaged Sinkhorn loop with eps-scaling (Algorithm); cost |x - y|^p / p,
+    eps = sigma^p, rho = reach^p.
 
     Returns dict(f, g, p, q, iters, n_scales, marginal_err, diameter, eps, converged).
     """
+    pexp = float(p)
     x, y = _pts(x), _pts(y)
     a, b = _f64(a), _f64(b)
     n, m, d = x.shape[0], y.shape[0], x.shape[1]
@@ -149,44 +163,46 @@ def sinkhorn(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0
         f, g, p, q = (_f64(v).copy() for v in init)
         flag = 1
     info = np.zeros(6)
-    _load().oracle_sinkhorn(n, m, d, _ptr(x), _ptr(a), _ptr(y), _ptr(b), float(blur),
-                            _reach(reach), float(scaling), float(diam or 0.0), int(extra_iters),
-                            float(tol), int(max_iters), int(check_every), flag, _ptr(f), _ptr(g),
-                            _ptr(p), _ptr(q), _ptr(info))
+    _load().oracle_sinkhorn_p(n, m, d, _ptr(x), _ptr(a), _ptr(y), _ptr(b), float(blur),
+                              _reach(reach), float(scaling), float(diam or 0.0), int(extra_iters),
+                              float(tol), int(max_iters), int(check_every), flag, pexp, _ptr(f),
+                              _ptr(g), _ptr(p), _ptr(q), _ptr(info))
     return dict(f=f, g=g, p=p, q=q, iters=int(info[0]), n_scales=int(info[1]),
                 marginal_err=float(info[2]), diameter=float(info[3]), eps=float(info[4]),
                 converged=bool(info[5]))
 
 
-def divergence(a, b, f, g, p, q, blur, reach=None):
-    """S_{eps,rho} in the dual form of eq. (6) at eps = blur**2."""
+def divergence(a, b, f, g, p, q, blur, reach=None, pexp=2.0):
+    """S_{eps,rho} in the dual form of eq. (6) at eps = blur**pexp."""
     a, b, f, g, p, q = (_f64(v) for v in (a, b, f, g, p, q))
-    return _load().oracle_divergence(a.size, b.size, _ptr(a), _ptr(b), _ptr(f), _ptr(g), _ptr(p),
-                                     _ptr(q), float(blur), _reach(reach))
+    return _load().oracle_divergence_p(a.size, b.size, _ptr(a), _ptr(b), _ptr(f), _ptr(g),
+                                       _ptr(p), _ptr(q), float(blur), _reach(reach), float(pexp))
 
 
-def ot_dual(x, a, y, b, f, g, eps, reach=None):
-    """Dual objective of eq. (3) at (f, g)."""
+def ot_dual(x, a, y, b, f, g, eps, reach=None, p=2.0):
+    """Dual objective of eq. (3) at (f, g) (cost |x - y|^p / p, rho = reach^p)."""
     x, y = _pts(x), _pts(y)
     a, b, f, g = (_f64(v) for v in (a, b, f, g))
-    return _load().oracle_ot_dual(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
-                                  _ptr(b), _ptr(f), _ptr(g), float(eps), _reach(reach))
+    return _load().oracle_ot_dual_p(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a),
+                                    _ptr(y), _ptr(b), _ptr(f), _ptr(g), float(eps), _reach(reach),
+                                    float(p))
 
 
-def ot_primal(x, a, y, b, f, g, eps, reach=None):
+def ot_primal(x, a, y, b, f, g, eps, reach=None, p=2.0):
     """Primal objective of eq. (2) at the plan of eq. (4) built from (f, g)."""
     x, y = _pts(x), _pts(y)
     a, b, f, g = (_f64(v) for v in (a, b, f, g))
-    return _load().oracle_ot_primal(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a), _ptr(y),
-                                    _ptr(b), _ptr(f), _ptr(g), float(eps), _reach(reach))
+    return _load().oracle_ot_primal_p(x.shape[0], y.shape[0], x.shape[1], _ptr(x), _ptr(a),
+                                      _ptr(y), _ptr(b), _ptr(f), _ptr(g), float(eps),
+                                      _reach(reach), float(p))
 
 
-def divergence_eq5(x, a, y, b, f, g, p, q, blur, reach=None):
+def divergence_eq5(x, a, y, b, f, g, p, q, blur, reach=None, pexp=2.0):
     """S by eq. (5), each OT term by its dual objective eq. (3) at the given potentials."""
-    eps = float(blur) ** 2
-    ab = ot_dual(x, a, y, b, f, g, eps, reach)
-    aa = ot_dual(x, a, x, a, p, p, eps, reach)
-    bb = ot_dual(y, b, y, b, q, q, eps, reach)
+    eps = float(blur) ** 2 if pexp == 2.0 else float(blur) ** float(pexp)
+    ab = ot_dual(x, a, y, b, f, g, eps, reach, p=pexp)
+    aa = ot_dual(x, a, x, a, p, p, eps, reach, p=pexp)
+    bb = ot_dual(y, b, y, b, q, q, eps, reach, p=pexp)
     ma, mb = float(np.sum(_f64(a))), float(np.sum(_f64(b)))
     return ab - 0.5 * aa - 0.5 * bb + 0.5 * eps * (ma - mb) ** 2
 
@@ -275,10 +291,11 @@ def label_transfer(x, a, y, b, labels, n_labels, blur, reach=None, flip_points=0
 
 
 def sinkhorn_divergence(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, extra_iters=0,
-                        tol=0.0, max_iters=0, check_every=1):
-    """Run the loop and return (S by eq. (6), the loop's result dict)."""
-    r = sinkhorn(x, a, y, b, blur, reach, scaling, diam, extra_iters, tol, max_iters, check_every)
-    S = divergence(a, b, r["f"], r["g"], r["p"], r["q"], blur, reach)
+                        tol=0.0, max_iters=0, check_every=1, p=2.0):
+    """Run the loop and return (S by eq. (6), the loop's result dict); cost |x - y|^p / p."""
+    r = sinkhorn(x, a, y, b, blur, reach, scaling, diam, extra_iters, tol, max_iters, check_every,
+                 p=p)
+    S = divergence(a, b, r["f"], r["g"], r["p"], r["q"], blur, reach, pexp=p)
     return S, r
 
 

@@ -15,11 +15,12 @@
  *
  * Notation (Section 2 of the paper):
  *   alpha = sum_i a_i delta_{x_i}, beta = sum_j b_j delta_{y_j}, x, y in R^D.
- *   Cost C(x, y) = |x - y|^2 / 2  (p = 2).
+ *   Cost C(x, y) = |x - y|^p / p, p = 2 unless stated (the entries with a
+ *   suffix _p take p in [1, 2]); eps = sigma^p, rho = reach^p.
  *   Dual vectors returned by the symmetric loop (Algorithm, "Return"):
  *     f = b^{beta->alpha} (length N),  g = a^{alpha->beta} (length M),
  *     p = a^{alpha<->alpha} (length N), q = b^{beta<->beta} (length M).
- *   eps = sigma^2, rho = reach^2, lambda = 1 / (1 + eps / rho)  (Algorithm).
+ *   eps = sigma^p, rho = reach^p, lambda = 1 / (1 + eps / rho)  (Algorithm).
  *   reach <= 0 or reach = +inf means the balanced problem: lambda = 1 and the
  *   rho -> inf limits of eqs. (2), (3) and (6).
  *
@@ -61,16 +62,21 @@ int oracle_num_threads(void) {
 
 static int is_balanced(double reach) { return !(reach > 0.0) || isinf(reach); }
 
-/* Cost C(x, y) = |x - y|^2 / 2 with p = 2 (Section 2, the cost function),
- * evaluated from coordinate differences, never from norms. */
-static double cost(const double *x, const double *y, int d) {
+/* Cost C(x, y) = |x - y|^p / p (Section 2, the cost function), evaluated from
+ * coordinate differences, never from norms; p = 2 is the default everywhere. */
+static double cost_p(const double *x, const double *y, int d, double pexp) {
     double s = 0.0;
     for (int k = 0; k < d; ++k) {
         double t = x[k] - y[k];
         s += t * t;
     }
-    return 0.5 * s;
+    return pexp == 2.0 ? 0.5 * s : pow(s, 0.5 * pexp) / pexp;
 }
+
+static double cost(const double *x, const double *y, int d) { return cost_p(x, y, d, 2.0); }
+
+/* sigma^p: eps from a scale, rho from the reach (the Algorithm's parameter lines) */
+static double power_p(double v, double pexp) { return pexp == 2.0 ? v * v : pow(v, pexp); }
 
 /* One softmin, the operation behind each of the four "tilde" updates of the
  * Algorithm:
@@ -79,8 +85,9 @@ static double cost(const double *x, const double *y, int d) {
  * The log-sum-exp is taken with its maximum factored out.  Columns with zero
  * weight contribute nothing (log 0 = -inf); a row with no positive weight
  * gets +inf.  buf: scratch of m doubles per thread, allocated here. */
-void oracle_softmin(int64_t n, int64_t m, int d, const double *r, const double *c,
-                    const double *w, const double *h, double eps, double lam, double *out) {
+void oracle_softmin_p(int64_t n, int64_t m, int d, const double *r, const double *c,
+                      const double *w, const double *h, double eps, double lam, double pexp,
+                      double *out) {
 #pragma omp parallel
     {
         double *s = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
@@ -89,7 +96,7 @@ void oracle_softmin(int64_t n, int64_t m, int d, const double *r, const double *
             double mx = -OR_INF;
             for (int64_t j = 0; j < m; ++j) {
                 if (w[j] > 0.0) {
-                    s[j] = log(w[j]) + (h[j] - cost(r + i * d, c + j * d, d)) / eps;
+                    s[j] = log(w[j]) + (h[j] - cost_p(r + i * d, c + j * d, d, pexp)) / eps;
                     if (s[j] > mx) mx = s[j];
                 } else {
                     s[j] = -OR_INF;
@@ -106,6 +113,11 @@ void oracle_softmin(int64_t n, int64_t m, int d, const double *r, const double *
         }
         free(s);
     }
+}
+
+void oracle_softmin(int64_t n, int64_t m, int d, const double *r, const double *c,
+                    const double *w, const double *h, double eps, double lam, double *out) {
+    oracle_softmin_p(n, m, d, r, c, w, h, eps, lam, 2.0, out);
 }
 
 /* Diameter heuristic of the Algorithm's parameter line, read as the diagonal
@@ -141,11 +153,11 @@ int oracle_schedule(double diameter, double blur, double scaling, double *sigmas
     return K + 1;
 }
 
-/* lambda of the Algorithm: 1 / (1 + (sigma / reach)^p) with p = 2. */
-static double damping(double sigma, double reach) {
+/* lambda of the Algorithm: 1 / (1 + eps / rho) = 1 / (1 + (sigma / reach)^p). */
+static double damping(double sigma, double reach, double pexp) {
     if (is_balanced(reach)) return 1.0;
     double t = sigma / reach;
-    return 1.0 / (1.0 + t * t);
+    return 1.0 / (1.0 + power_p(t, pexp));
 }
 
 /* Relative L1 error between a transport plan's row sums and their target.
@@ -154,12 +166,12 @@ static double damping(double sigma, double reach) {
  * Target: a_i exp(-f_i / rho), or a_i when balanced (first-order condition of
  * eq. (3)). */
 static double marginal_error(int64_t n, const double *a, const double *f, const double *ft,
-                             double eps, double lam, double reach) {
+                             double eps, double lam, double reach, double pexp) {
     double num = 0.0, den = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         if (!(a[i] > 0.0)) continue;
         double r = a[i] * exp((f[i] - ft[i] / lam) / eps);
-        double t = is_balanced(reach) ? a[i] : a[i] * exp(-f[i] / (reach * reach));
+        double t = is_balanced(reach) ? a[i] : a[i] * exp(-f[i] / power_p(reach, pexp));
         num += fabs(r - t);
         den += t;
     }
@@ -180,10 +192,11 @@ static double marginal_error(int64_t n, const double *a, const double *f, const 
  *     error, diameter used, final eps, converged flag].
  * Returns the number of iterations run.
  */
-int oracle_sinkhorn(int64_t n, int64_t m, int d, const double *x, const double *a, const double *y,
-                    const double *b, double blur, double reach, double scaling, double diameter,
-                    int extra_iters, double tol, int max_iters, int check_every, int init,
-                    double *f, double *g, double *p, double *q, double *info) {
+int oracle_sinkhorn_p(int64_t n, int64_t m, int d, const double *x, const double *a,
+                      const double *y, const double *b, double blur, double reach, double scaling,
+                      double diameter, int extra_iters, double tol, int max_iters,
+                      int check_every, int init, double pexp, double *f, double *g, double *p,
+                      double *q, double *info) {
     if (!(diameter > 0.0)) diameter = oracle_diameter(n, m, d, x, y);
     int L = oracle_schedule(diameter, blur, scaling, NULL, 0);
     double *sig = (double *)malloc(sizeof(double) * (size_t)L);
@@ -203,24 +216,24 @@ int oracle_sinkhorn(int64_t n, int64_t m, int d, const double *x, const double *
     int total = L + (extra_iters > 0 ? extra_iters : 0);
     int cap = total + (tol > 0.0 ? (max_iters > 0 ? max_iters : 0) : 0);
     if (check_every < 1) check_every = 1;
-    double err = -1.0, eps = blur * blur;
+    double err = -1.0, eps = power_p(blur, pexp);
     int it = 0, converged = 0;
     for (; it < cap; ++it) {
         double sigma = it < L ? sig[it] : blur;
-        eps = sigma * sigma;
-        double lam = damping(sigma, reach);
+        eps = power_p(sigma, pexp);
+        double lam = damping(sigma, reach, pexp);
         /* the four tilde updates, all from the values before this iteration */
-        oracle_softmin(n, n, d, x, x, a, p, eps, lam, pt); /* a~^{alpha<->alpha}_i */
-        oracle_softmin(m, m, d, y, y, b, q, eps, lam, qt); /* b~^{beta<->beta}_j  */
-        oracle_softmin(m, n, d, y, x, a, f, eps, lam, gt); /* a~^{alpha->beta}_j  */
-        oracle_softmin(n, m, d, x, y, b, g, eps, lam, ft); /* b~^{beta->alpha}_i  */
+        oracle_softmin_p(n, n, d, x, x, a, p, eps, lam, pexp, pt); /* a~^{alpha<->alpha}_i */
+        oracle_softmin_p(m, m, d, y, y, b, q, eps, lam, pexp, qt); /* b~^{beta<->beta}_j  */
+        oracle_softmin_p(m, n, d, y, x, a, f, eps, lam, pexp, gt); /* a~^{alpha->beta}_j  */
+        oracle_softmin_p(n, m, d, x, y, b, g, eps, lam, pexp, ft); /* b~^{beta->alpha}_i  */
         int check = (it == cap - 1);
         if (tol > 0.0 && it >= total && ((it - total + 1) % check_every == 0)) check = 1;
         if (check) {
-            double e1 = marginal_error(n, a, f, ft, eps, lam, reach);
-            double e2 = marginal_error(m, b, g, gt, eps, lam, reach);
-            double e3 = marginal_error(n, a, p, pt, eps, lam, reach);
-            double e4 = marginal_error(m, b, q, qt, eps, lam, reach);
+            double e1 = marginal_error(n, a, f, ft, eps, lam, reach, pexp);
+            double e2 = marginal_error(m, b, g, gt, eps, lam, reach, pexp);
+            double e3 = marginal_error(n, a, p, pt, eps, lam, reach, pexp);
+            double e4 = marginal_error(m, b, q, qt, eps, lam, reach, pexp);
             err = fmax(fmax(e1, e2), fmax(e3, e4));
         }
         /* averaging step of the Algorithm */
@@ -254,44 +267,64 @@ int oracle_sinkhorn(int64_t n, int64_t m, int d, const double *x, const double *
     return it;
 }
 
+int oracle_sinkhorn(int64_t n, int64_t m, int d, const double *x, const double *a, const double *y,
+                    const double *b, double blur, double reach, double scaling, double diameter,
+                    int extra_iters, double tol, int max_iters, int check_every, int init,
+                    double *f, double *g, double *p, double *q, double *info) {
+    return oracle_sinkhorn_p(n, m, d, x, a, y, b, blur, reach, scaling, diameter, extra_iters, tol,
+                             max_iters, check_every, init, 2.0, f, g, p, q, info);
+}
+
 /* Sinkhorn divergence in dual form, eq. (6), at eps = blur^2:
  *   S = -(rho + eps/2) <a, e^{-f/rho} - e^{-p/rho}> - (rho + eps/2) <b, e^{-g/rho} - e^{-q/rho}>.
  * Balanced (rho -> inf): S = <a, f - p> + <b, g - q>. */
-double oracle_divergence(int64_t n, int64_t m, const double *a, const double *b, const double *f,
-                         const double *g, const double *p, const double *q, double blur,
-                         double reach) {
-    double eps = blur * blur;
+double oracle_divergence_p(int64_t n, int64_t m, const double *a, const double *b, const double *f,
+                           const double *g, const double *p, const double *q, double blur,
+                           double reach, double pexp) {
+    double eps = power_p(blur, pexp);
     double s = 0.0;
     if (is_balanced(reach)) {
         for (int64_t i = 0; i < n; ++i) s += a[i] * (f[i] - p[i]);
         for (int64_t j = 0; j < m; ++j) s += b[j] * (g[j] - q[j]);
         return s;
     }
-    double rho = reach * reach;
+    double rho = power_p(reach, pexp);
     for (int64_t i = 0; i < n; ++i) s += a[i] * exp(-p[i] / rho) * expm1(-(f[i] - p[i]) / rho);
     for (int64_t j = 0; j < m; ++j) s += b[j] * exp(-q[j] / rho) * expm1(-(g[j] - q[j]) / rho);
     return -(rho + 0.5 * eps) * s;
+}
+
+double oracle_divergence(int64_t n, int64_t m, const double *a, const double *b, const double *f,
+                         const double *g, const double *p, const double *q, double blur,
+                         double reach) {
+    return oracle_divergence_p(n, m, a, b, f, g, p, q, blur, reach, 2.0);
 }
 
 /* Dual objective of eq. (3) for OT_{eps,rho}(alpha, beta) at (f, g):
  *   rho <a, 1 - e^{-f/rho}> + rho <b, 1 - e^{-g/rho}>
  *   + eps <a (x) b, 1 - exp((f_i + g_j - C_ij) / eps)>.
  * Balanced: <a, f> + <b, g> + eps <a (x) b, 1 - exp(...)>. */
-double oracle_ot_dual(int64_t n, int64_t m, int d, const double *x, const double *a, const double *y,
-                      const double *b, const double *f, const double *g, double eps, double reach) {
+double oracle_ot_dual_p(int64_t n, int64_t m, int d, const double *x, const double *a,
+                        const double *y, const double *b, const double *f, const double *g,
+                        double eps, double reach, double pexp) {
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int bal = is_balanced(reach);
-    double rho = bal ? 0.0 : reach * reach;
+    double rho = bal ? 0.0 : power_p(reach, pexp);
     for (int64_t i = 0; i < n; ++i) s1 += bal ? a[i] * f[i] : rho * a[i] * (-expm1(-f[i] / rho));
     for (int64_t j = 0; j < m; ++j) s2 += bal ? b[j] * g[j] : rho * b[j] * (-expm1(-g[j] / rho));
 #pragma omp parallel for reduction(+ : s3) schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double r = 0.0;
         for (int64_t j = 0; j < m; ++j)
-            r += a[i] * b[j] * (-expm1((f[i] + g[j] - cost(x + i * d, y + j * d, d)) / eps));
+            r += a[i] * b[j] * (-expm1((f[i] + g[j] - cost_p(x + i * d, y + j * d, d, pexp)) / eps));
         s3 += r;
     }
     return s1 + s2 + eps * s3;
+}
+
+double oracle_ot_dual(int64_t n, int64_t m, int d, const double *x, const double *a, const double *y,
+                      const double *b, const double *f, const double *g, double eps, double reach) {
+    return oracle_ot_dual_p(n, m, d, x, a, y, b, f, g, eps, reach, 2.0);
 }
 
 /* KL(u, v) = sum u log(u / v) - u + v, with 0 log 0 = 0 (Section 2). */
@@ -304,9 +337,9 @@ static double kl_term(double u, double v) {
  *   pi_ij = a_i b_j exp((f_i + g_j - C_ij) / eps):
  *   <pi, C> + eps KL(pi, a (x) b) + rho KL(pi 1, a) + rho KL(pi^T 1, b).
  * Balanced: the two marginal terms are constraints and are left out. */
-double oracle_ot_primal(int64_t n, int64_t m, int d, const double *x, const double *a,
-                        const double *y, const double *b, const double *f, const double *g,
-                        double eps, double reach) {
+double oracle_ot_primal_p(int64_t n, int64_t m, int d, const double *x, const double *a,
+                          const double *y, const double *b, const double *f, const double *g,
+                          double eps, double reach, double pexp) {
     double *row = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
     double *col = (double *)calloc((size_t)(m ? m : 1), sizeof(double));
     double lin = 0.0, ent = 0.0;
@@ -314,7 +347,7 @@ double oracle_ot_primal(int64_t n, int64_t m, int d, const double *x, const doub
         for (int64_t j = 0; j < m; ++j) {
             double ab = a[i] * b[j];
             if (!(ab > 0.0)) continue;
-            double c = cost(x + i * d, y + j * d, d);
+            double c = cost_p(x + i * d, y + j * d, d, pexp);
             double pij = ab * exp((f[i] + g[j] - c) / eps);
             lin += pij * c;
             ent += kl_term(pij, ab);
@@ -324,7 +357,7 @@ double oracle_ot_primal(int64_t n, int64_t m, int d, const double *x, const doub
     }
     double s = lin + eps * ent;
     if (!is_balanced(reach)) {
-        double rho = reach * reach, k1 = 0.0, k2 = 0.0;
+        double rho = power_p(reach, pexp), k1 = 0.0, k2 = 0.0;
         for (int64_t i = 0; i < n; ++i) k1 += kl_term(row[i], a[i]);
         for (int64_t j = 0; j < m; ++j) k2 += kl_term(col[j], b[j]);
         s += rho * (k1 + k2);
@@ -332,6 +365,12 @@ double oracle_ot_primal(int64_t n, int64_t m, int d, const double *x, const doub
     free(row);
     free(col);
     return s;
+}
+
+double oracle_ot_primal(int64_t n, int64_t m, int d, const double *x, const double *a,
+                        const double *y, const double *b, const double *f, const double *g,
+                        double eps, double reach) {
+    return oracle_ot_primal_p(n, m, d, x, a, y, b, f, g, eps, reach, 2.0);
 }
 
 /* Row and column sums of the plan of eq. (4). */

@@ -633,3 +633,73 @@ def test_label_transfer_flips_and_outliers():
     assert rev.sum() > 10
     assert score0[:45][rev].max() < 0.6 < 1.2 < score0[:45][~rev].min()
     assert np.all(score0[~inl] < 1e-6)
+
+
+# ------------------------------------------------------ general exponent p ---
+
+@pytest.mark.parametrize("pexp", [1.0, 1.5])
+def test_cost_p_softmin_single_column(pexp):
+    # m = 1: out_i = lam (C(x_i, y) - h - eps log w) with C = |x - y|^p / p
+    rng = np.random.default_rng(80)
+    x, y = rng.uniform(size=(7, 3)), rng.uniform(size=(1, 3))
+    eps, lam, w, h = 0.04, 0.8, 0.3, 0.25
+    C = np.sqrt(((x - y) ** 2).sum(1)) ** pexp / pexp
+    out = oracle.softmin(x, y, [w], [h], eps, lam, p=pexp)
+    np.testing.assert_allclose(out, lam * (C - h - eps * math.log(w)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("pexp", [1.0, 1.5])
+def test_cost_p_dirac_balanced_and_unbalanced(pexp):
+    # One Dirac each: balanced S = C for any eps; unbalanced from the closed-form minimiser of
+    # eq. (2), whose derivation only uses the scalars C, eps = blur^p and rho = reach^p.
+    x, y = np.array([[0.3, -0.2]]), np.array([[-0.1, 0.4]])
+    C = np.sqrt(((x - y) ** 2).sum()) ** pexp / pexp
+    S, r = oracle.sinkhorn_divergence(x, [1.0], y, [1.0], 0.3, scaling=0.5, tol=1e-14,
+                                      max_iters=20000, p=pexp)
+    assert S == pytest.approx(C, rel=1e-12)
+    blur, reach = 0.3, 0.7
+    eps, rho = blur ** pexp, reach ** pexp
+    for a, b in ((1.0, 1.0), (0.6, 1.7)):
+        expect = (_dirac_ot(a, b, C, eps, rho) - 0.5 * _dirac_ot(a, a, 0.0, eps, rho)
+                  - 0.5 * _dirac_ot(b, b, 0.0, eps, rho) + 0.5 * eps * (a - b) ** 2)
+        S, r = oracle.sinkhorn_divergence(x, [a], y, [b], blur, reach, scaling=0.5, tol=1e-14,
+                                          max_iters=20000, p=pexp)
+        assert r["converged"]
+        assert S == pytest.approx(expect, rel=1e-10)
+
+
+@pytest.mark.parametrize("pexp", [1.0, 1.5])
+def test_cost_p_sorted_matching_1d(pexp):
+    # Uniform 1-D measures: OT_0 is the sorted matching for any convex cost (p >= 1), and
+    # |S_eps - OT_0| <= eps log n (entropic bounds of the three OT terms).
+    rng = np.random.default_rng(81)
+    n = 6
+    x, y = rng.uniform(size=(n, 1)), rng.uniform(size=(n, 1)) + 0.3
+    ot0 = np.mean(np.abs(np.sort(x[:, 0]) - np.sort(y[:, 0])) ** pexp / pexp)
+    blur = 0.01 ** (1.0 / pexp)  # eps = 0.01
+    S, r = oracle.sinkhorn_divergence(x, _u(n), y, _u(n), blur, scaling=0.7, tol=1e-10,
+                                      max_iters=200000, p=pexp)
+    assert r["converged"]
+    assert abs(S - ot0) <= blur ** pexp * math.log(n)
+
+
+@pytest.mark.parametrize("reach", [None, 0.5])
+def test_cost_p_strong_duality(reach):
+    # At the fixed point of the loop for p = 1, the primal eq. (2) at the plan of eq. (4)
+    # equals the dual eq. (3) (strong duality), for the cross and both self problems.
+    rng = np.random.default_rng(82)
+    x, y = rng.uniform(size=(7, 2)), rng.uniform(size=(8, 2))
+    a, b = _w(7, 83), _w(8, 84)
+    blur = 0.15
+    S, r = oracle.sinkhorn_divergence(x, a, y, b, blur, reach, scaling=0.6, tol=1e-14,
+                                      max_iters=50000, p=1.0)
+    assert r["converged"]
+    eps = blur
+    for (u, wu, v, wv, fu, fv) in ((x, a, y, b, r["f"], r["g"]), (x, a, x, a, r["p"], r["p"]),
+                                   (y, b, y, b, r["q"], r["q"])):
+        prim = oracle.ot_primal(u, wu, v, wv, fu, fv, eps, reach, p=1.0)
+        dual = oracle.ot_dual(u, wu, v, wv, fu, fv, eps, reach, p=1.0)
+        assert prim == pytest.approx(dual, rel=1e-9, abs=1e-12)
+    # eq. (6) equals eq. (5) through the duals
+    S5 = oracle.divergence_eq5(x, a, y, b, r["f"], r["g"], r["p"], r["q"], blur, reach, pexp=1.0)
+    assert S == pytest.approx(S5, rel=1e-9, abs=1e-12)
