@@ -23,6 +23,7 @@ broadcast are inside the timed region).
 200k x 200k fibre solve (reach 20 mm); Gpair/s of the plan-weighted kernels.
 --workload labels200k: label transfer from a 200k-fibre labelled atlas to a 200k-fibre
 subject (random fibre directions, 1 % aberrant fibres) with flip augmentation.
+--workload pcost200k: full solve with the cost |x - y| (p = 1) on 200k x 200k 3-D clouds.
 
 Prints one JSON line:
   value       = softmin point pairs evaluated / wall time of the timed steps (Gpair/s)
@@ -282,6 +283,45 @@ def bench_labels(args, skh, synth):
     return 0
 
 
+def bench_pcost(args, skh, synth):
+    """Full solve with the cost |x - y| (p = 1) on 200k x 200k 3-D blob clouds: the VALU
+    softmin (direct coordinate differences, a square root, one exponential per pair)."""
+    import torch
+    n = args.n
+    print(f"[bench] generating {n} x {n} 3-D blob clouds", file=sys.stderr, flush=True)
+    x, a, y, b = synth.blob_pair(n, seed=0)
+    X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+    kw = dict(blur=0.01, reach=None, scaling=0.9, potentials=True, timing=True, p=1.0)
+    agg = solve_steps(skh, X, A, Y, B, args.steps, args.warmup, "p = 1", **kw)
+    st = agg["stats"]
+    kern_s = agg["ms_softmin"] / agg["launches"] / 1e3
+    ppl = agg["pairs"] / agg["launches"]
+    # VALU issue bound: per pair the formula needs d subtractions and d FMAs for |x - y|^2,
+    # the square root, the exponent FMA, the maximum, the subtraction of the level, the
+    # exponential and the sum (2 d + 6 lane operations, d = 3); without packed FP32 a
+    # SIMD issues 16 lanes per clock, transcendentals included: 256 CUs x 4 SIMDs x 16
+    # lanes x 2.4 GHz = 39.3e12 lane operations per second
+    ops = 2 * 3 + 6
+    peak = 256 * 4 * 16 * 2.4e9 / 1e12
+    ach = ops * ppl / kern_s / 1e12
+    out = {"metric": "Gpair/s of the log-sum-exp softmin, cost |x - y| (full S_eps solve, "
+                     f"{n} x {n} 3-D clouds)",
+           "value": round(agg["pairs"] / agg["dt"] / 1e9, 3), "unit": "Gpair/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(agg["dt"] / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3-D Gaussian blob clouds n=m={n}, cost |x-y| (p = 1), "
+                                  "blur 0.01, balanced, scaling 0.9, dense",
+                      "iterations": st["iters"]},
+           "S": agg["S"], "softmin_kernel_gpair_s": round(ppl / kern_s / 1e9, 3),
+           "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 2),
+                        "unit": "Tops/s", "frac": round(ach / peak, 4), "traffic": None,
+                        "ops_per_pair": ops, "avg_launch_ms": round(kern_s * 1e3, 4),
+                        "kernel": "k_softmin_pcost<4, p = 1>"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +329,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
     ap.add_argument("--workload", default="fibers200k",
-                    choices=["fibers200k", "multiscale1m", "grad200k", "labels200k"])
+                    choices=["fibers200k", "multiscale1m", "grad200k", "labels200k",
+                             "pcost200k"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison solve")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
@@ -325,6 +366,8 @@ def main() -> int:
         return bench_gradients(args, skh, synth)
     if args.workload == "labels200k":
         return bench_labels(args, skh, synth)
+    if args.workload == "pcost200k":
+        return bench_pcost(args, skh, synth)
     print(f"[bench] generating {args.n} x {args.n} fibre clouds", file=sys.stderr, flush=True)
     x, a, y, b = synth.fiber_pair(args.n, args.bundles, seed=0)
     dev = torch.device("cuda:0")

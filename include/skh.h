@@ -6,8 +6,8 @@
  * Tractograms" (MICCAI 2019, arXiv 2107.02010), Section 2:
  *
  *   alpha = sum_i a_i delta_{x_i},  beta = sum_j b_j delta_{y_j},  x, y in R^D,
- *   cost C(x, y) = |x - y|^2 / 2  (p = 2),
- *   eps = sigma^2, rho = reach^2, lambda = 1 / (1 + eps / rho).
+ *   cost C(x, y) = |x - y|^2 / 2  (p = 2; skh_params.cost_p selects |x - y|^p / p),
+ *   eps = sigma^2, rho = reach^2, lambda = 1 / (1 + eps / rho)  (sigma^p, reach^p).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -84,6 +84,10 @@ typedef struct skh_params {
                             <= 0: keep every block */
     double start_scale;  /* init != COLD: largest scale of the schedule (start_scale q^k, then
                             blur); <= 0: the diameter rule.  A cold run ignores it */
+    double cost_p;       /* exponent p of the cost C(x, y) = |x - y|^p / p (Section 2), in [1, 2];
+                            eps = sigma^p, rho = reach^p, lambda = 1 / (1 + eps / rho).  0 is
+                            read as 2.  p != 2: dense FP32 solves only (no multiscale, no BF16
+                            split); the plan, gradient and label-transfer entries use p = 2 */
     const int32_t *labels_x; /* clustered paths (BF16 split, multiscale): optional cluster label
                             of every point of x in [0, k) (device, n values), k = n_clusters or
                             ceil(sqrt(n)); replaces the K-means (points are grouped, centres
@@ -128,7 +132,7 @@ typedef struct skh_stats {
  * diameter = 0 (auto), tol = 0 (schedule mode), extra_iters = 0,
  * max_iters = 1000, check_every = 5, precision = SKH_FP32, init = 0, timing = 0,
  * multiscale = 0, jump_scale = 0, trunc_theta = 20, start_scale = 0,
- * n_clusters = 0, kmeans_iters = 10, fixed = 0. */
+ * n_clusters = 0, kmeans_iters = 10, fixed = 0, cost_p = 2. */
 void skh_params_default(skh_params *p);
 
 /* Creates a context on HIP device `device` bound to stream `hip_stream`

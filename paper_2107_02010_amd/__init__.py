@@ -121,7 +121,7 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
                         multiscale: bool = False, jump_scale: float = 0.0,
                         trunc_theta: float = 20.0, n_clusters: int = 0, kmeans_iters: int = 10,
                         start_scale: float = 0.0, checked_init: bool = False, fixed: int = 0,
-                        labels=None):
+                        labels=None, p: float = 2.0):
     """S_{eps,rho}(alpha, beta) of eq. (5), through eq. (6) after the averaged symmetric loop.
 
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
@@ -136,6 +136,8 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     timing=True records HIP events around every softmin launch (stats["ms_softmin"]).
     multiscale=True: K-means coarse phase while sigma > jump_scale (0: RMS cluster radius,
     < 0: none), then cluster-block truncation at weight e^{-trunc_theta} (<= 0: none).
+    p: exponent of the cost |x - y|^p / p in [1, 2] (eps = blur^p, rho = reach^p); p != 2
+    runs the dense FP32 path.
     """
     x, y = _as_points(x, "x"), _as_points(y, "y")
     if x.shape[1] != y.shape[1]:
@@ -147,6 +149,7 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
                        precision, timing, multiscale, jump_scale, trunc_theta, n_clusters,
                        kmeans_iters)
     P.fixed = int(fixed)
+    P.cost_p = float(p)
     if labels is not None:
         lx, ly = labels
         for t, k, nm in ((lx, n, "labels_x"), (ly, m, "labels_y")):

@@ -40,7 +40,7 @@ _c_i32, _c_i64, _c_d, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, c
 class SkhParams(ctypes.Structure):
     _fields_ = [
         ("blur", _c_d), ("reach", _c_d), ("scaling", _c_d), ("diameter", _c_d), ("tol", _c_d),
-        ("jump_scale", _c_d), ("trunc_theta", _c_d), ("start_scale", _c_d),
+        ("jump_scale", _c_d), ("trunc_theta", _c_d), ("start_scale", _c_d), ("cost_p", _c_d),
         ("labels_x", _c_vp), ("labels_y", _c_vp),
         ("extra_iters", _c_i32), ("max_iters", _c_i32), ("check_every", _c_i32),
         ("precision", _c_i32), ("init", _c_i32), ("timing", _c_i32), ("multiscale", _c_i32),

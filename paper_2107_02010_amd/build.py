@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libskh.so")
 
-SOURCES = ["softmin.hip", "softmin_bf16.hip", "plan.hip", "kmeans.hip", "multiscale.hip",
+SOURCES = ["softmin.hip", "softmin_bf16.hip", "softmin_pcost.hip", "plan.hip", "kmeans.hip", "multiscale.hip",
            "aux_kernels.hip", "warmstart.hip", "api.cpp", "ws_api.cpp"]
 ARCH = os.environ.get("SKH_OFFLOAD_ARCH", "gfx950")
 

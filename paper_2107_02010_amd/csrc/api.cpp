@@ -105,6 +105,7 @@ void skh_params_default(skh_params *p) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));
     p->blur = 0.05;
+    p->cost_p = 2.0;
     p->reach = INFINITY;
     p->scaling = 0.9;
     p->diameter = 0.0;
@@ -327,7 +328,13 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (!kp) return fail(ctx, SKH_EINVAL, "the BF16 split path needs d <= 60");
     const int check_every = P.check_every < 1 ? 1 : P.check_every;
     const bool balanced = is_balanced(P.reach);
-    const double rho = balanced ? 0.0 : P.reach * P.reach;
+    // cost |x - y|^p / p: eps = sigma^p, rho = reach^p (p = 2 unless given)
+    const double pc = P.cost_p == 0.0 ? 2.0 : P.cost_p;
+    if (!(pc >= 1.0 && pc <= 2.0)) return fail(ctx, SKH_EINVAL, "cost_p must be in [1, 2]");
+    if (pc != 2.0 && (split || ms))
+        return fail(ctx, SKH_EINVAL, "cost_p != 2 runs on the dense FP32 path only");
+    auto powp = [pc](double v) { return pc == 2.0 ? v * v : std::pow(v, pc); };
+    const double rho = balanced ? 0.0 : powp(P.reach);
 
     DeviceGuard guard(ctx->device);
     hipStream_t s = ctx->stream;
@@ -418,6 +425,10 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     SKH_HIP(skh::launch_pack(x, a, n, d, kp, lohi + 128, Xp, hnx, lwx, s));
     SKH_HIP(skh::launch_pack(y, b, m, d, kp, lohi + 128, Yp, hny, lwy, s));
+    if (pc != 2.0) {  // no |x|^2/2 expansion terms for this cost
+        SKH_HIP(hipMemsetAsync(hnx, 0, sizeof(float) * n, s));
+        SKH_HIP(hipMemsetAsync(hny, 0, sizeof(float) * m, s));
+    }
     // point sets of the fine loop: caller order (dense FP32) or cluster order
     int64_t nn = n, mm = m;
     const float *rowx = Xp, *rowy = Yp, *hnX = hnx, *hnY = hny, *lwX = lwx, *lwY = lwy, *wX = a,
@@ -501,6 +512,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     skh::SoftminBatch batch{};
     batch.n_jobs = 4;
     batch.d = d;
+    batch.cost_p = (float)pc;
     // job 0: a~^{aa} (rows x, cols x); job 1: b~^{bb} (rows y, cols y);
     // job 2: a~^{a->b} (rows y, cols x); job 3: b~^{b->a} (rows x, cols y).
     const int64_t nr[4] = {nn, mm, mm, nn}, nc[4] = {nn, mm, nn, mm};
@@ -611,7 +623,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     if (ms && t_jump > 0) {
         float *Fc = cpot[0], *Gc = cpot[1], *Pc = cpot[2], *Qc = cpot[3];
         for (int k = 0; k < 4; ++k) SKH_HIP(hipMemsetAsync(cpot[k], 0, (k % 2 ? ky : kx) * sizeof(float), s));
-        const double e0 = sigma_at(0) * sigma_at(0);
+        const double e0 = powp(sigma_at(0));
         SKH_HIP(skh::launch_col_offsets(cx.lwC, Pc, cx.hnC, kx, e0, uc[0], s));
         SKH_HIP(skh::launch_col_offsets(cy.lwC, Qc, cy.hnC, ky, e0, uc[1], s));
         SKH_HIP(skh::launch_col_offsets(cx.lwC, Fc, cx.hnC, kx, e0, uc[2], s));
@@ -650,16 +662,16 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         csy.u_cross = uc[3];
         const double cpairs = (double)kx * kx + (double)ky * ky + 2.0 * (double)kx * ky;
         for (int it = 0; it < t_jump; ++it) {
-            const double sigma = sigma_at(it), eps = sigma * sigma, sn = sigma_at(it + 1);
+            const double sigma = sigma_at(it), eps = powp(sigma), sn = sigma_at(it + 1);
             cbatch.kscale = (float)(kLog2e / eps);
             SKH_HIP(skh::launch_softmin(cbatch, kp, SKH_FP32, cwgs, s));
-            SKH_HIP(skh::launch_iteration_finish(csx, csy, eps, damping(sigma, P.reach), rho,
-                                                 balanced ? 1 : 0, sn * sn, 0, cacc, s));
+            SKH_HIP(skh::launch_iteration_finish(csx, csy, eps, damping(sigma, P.reach, pc), rho,
+                                                 balanced ? 1 : 0, powp(sn), 0, cacc, s));
             pairs += cpairs;
         }
         // jump: one softmin of the fine points against the other cloud's coarse
         // measure, at the scale of the last coarse iteration
-        const double sj = sigma_at(t_jump - 1), ej = sj * sj, lj = damping(sj, P.reach);
+        const double sj = sigma_at(t_jump - 1), ej = powp(sj), lj = damping(sj, P.reach, pc);
         SKH_HIP(skh::launch_col_offsets(cx.lwC, Pc, cx.hnC, kx, ej, ju[0], s));
         SKH_HIP(skh::launch_col_offsets(cy.lwC, Qc, cy.hnC, ky, ej, ju[1], s));
         SKH_HIP(skh::launch_col_offsets(cx.lwC, Fc, cx.hnC, kx, ej, ju[2], s));
@@ -683,7 +695,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     // ---- Fine phase ----
     {
-        const double e0 = sigma_at(t_jump) * sigma_at(t_jump);
+        const double e0 = powp(sigma_at(t_jump));
         SKH_HIP(skh::launch_col_offsets(lwX, Pp, hnX, nn, e0, u[0], s));
         SKH_HIP(skh::launch_col_offsets(lwY, Q, hnY, mm, e0, u[1], s));
         SKH_HIP(skh::launch_col_offsets(lwX, F, hnX, nn, e0, u[2], s));
@@ -750,13 +762,13 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         int rc = ensure_events(ctx, 2 * (size_t)cap);
         if (rc) return rc;
     }
-    double err = -1.0, eps = P.blur * P.blur;
+    double err = -1.0, eps = powp(P.blur);
     int it = t_jump, checks = 0, launches = 0;
     bool converged = false;
     for (; it < cap; ++it) {
         const double sigma = sigma_at(it);
-        eps = sigma * sigma;
-        const double lam = damping(sigma, P.reach);
+        eps = powp(sigma);
+        const double lam = damping(sigma, P.reach, pc);
         const double sn = sigma_at(it + 1);
         if (ms) {  // cluster-block truncation from the current dual vectors
             SKH_HIP(skh::launch_cluster_max(F, wX, cx.poff, kx, cmax[0], s));
@@ -796,7 +808,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         ++launches;
         bool check = (it == cap - 1);
         if (P.tol > 0.0 && it >= total && ((it - total + 1) % check_every == 0)) check = true;
-        SKH_HIP(skh::launch_iteration_finish(sx, sy, eps, lam, rho, balanced ? 1 : 0, sn * sn,
+        SKH_HIP(skh::launch_iteration_finish(sx, sy, eps, lam, rho, balanced ? 1 : 0, powp(sn),
                                              check ? 1 : 0, acc, s));
         {
             int rc = refresh_slots();
@@ -825,7 +837,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         }
     }
 
-    // eq. (6) at eps = blur^2, FP64 on the device.
+    // eq. (6) at eps = blur^p, FP64 on the device.
     int nbd = 0;
     SKH_HIP(skh::launch_divergence_terms(wX, F, Pp, nn, wY, G, Q, mm, rho, balanced ? 1 : 0, acc,
                                          &nbd, s));
@@ -843,7 +855,7 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     SKH_HIP(hipStreamSynchronize(s));
     double S = *reinterpret_cast<const double *>(hb + 1024);
     if (ms) pairs += (double)*reinterpret_cast<const unsigned long long *>(hb + 1088);
-    const double eps_blur = P.blur * P.blur;
+    const double eps_blur = powp(P.blur);
     if (!balanced) S = -(rho + 0.5 * eps_blur) * S;
     if (S_out) *S_out = S;
     double ms_softmin = 0.0;
@@ -1067,6 +1079,8 @@ int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, 
         return fail(ctx, SKH_EINVAL, "flip_points must be 0 or divide d");
     const int64_t na = flip_points ? 2 * n : n;
     if (na > kMaxPoints) return fail(ctx, SKH_EINVAL, "2 n exceeds the point limit");
+    if (params->cost_p != 0.0 && params->cost_p != 2.0)
+        return fail(ctx, SKH_EINVAL, "label transfer uses the cost |x - y|^2 / 2");
     if (params->init != SKH_INIT_COLD || params->fixed || params->labels_x || params->labels_y)
         return fail(ctx, SKH_EINVAL,
                     "label transfer runs its own cold solve (init, fixed, labels_x/y unset)");

@@ -87,10 +87,11 @@ inline int ensure_ws(skh_ctx *ctx, int slot, size_t bytes) {
 inline bool is_balanced(double reach) { return !(reach > 0.0) || std::isinf(reach); }
 
 // lambda of the Algorithm, 1 / (1 + (sigma / reach)^2).
-inline double damping(double sigma, double reach) {
+// lambda = 1 / (1 + eps / rho) = 1 / (1 + (sigma / reach)^p)
+inline double damping(double sigma, double reach, double p = 2.0) {
     if (is_balanced(reach)) return 1.0;
     const double t = sigma / reach;
-    return 1.0 / (1.0 + t * t);
+    return 1.0 / (1.0 + (p == 2.0 ? t * t : std::pow(t, p)));
 }
 
 // The scale list [d, d q, ..., blur] of the Algorithm's loop header:

@@ -57,7 +57,7 @@ struct SoftminBatch {
     int n_jobs;
     int d;         // coordinates per point; slot d carries the augmented term
     float kscale;  // log2(e) / eps
-    int pad;
+    float cost_p;  // exponent p of the cost |x - y|^p / p; 0 or 2: the p = 2 kernels
 };
 
 // Builds chunking for a batch of jobs so that the launch holds enough
@@ -67,6 +67,8 @@ int plan_softmin_batch(SoftminBatch &b, int target_wgs);
 hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
                           hipStream_t s);
 hipError_t launch_softmin_bf16(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s);
+// cost |x - y|^p / p with p != 2 (dense FP32 path, one row per thread)
+hipError_t launch_softmin_pcost(const SoftminBatch &b, int kp, int total_wgs, hipStream_t s);
 // u -> three bf16 terms in slots d..d+2 of a packed hi plane (split path)
 hipError_t launch_u_slots(const float *u, int n, int kp, int d, __hip_bfloat16 *hi,
                           hipStream_t s);

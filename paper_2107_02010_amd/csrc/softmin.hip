@@ -203,6 +203,7 @@ int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
 hipError_t launch_softmin(const SoftminBatch &b, int kp, int precision, int total_wgs,
                           hipStream_t s) {
     (void)precision;
+    if (b.cost_p != 0.0f && b.cost_p != 2.0f) return launch_softmin_pcost(b, kp, total_wgs, s);
     dim3 grid(total_wgs), block(256);
     switch (kp) {
     case 4: hipLaunchKernelGGL(k_softmin_f32<4>, grid, block, 0, s, b); break;
