@@ -177,6 +177,29 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
                             float *q, skh_stats *stats);
 
 /*
+ * K independent problems solved together (a batched multi-pair call; the
+ * barycenter of Section 3 runs its maps' cross loops this way): pair k is
+ * (alpha_k, beta_k) with the points [x_off[k], x_off[k+1]) of x, a and
+ * [y_off[k], y_off[k+1]) of y, b.  Every iteration runs the four softmins of
+ * all pairs in one launch, each row tile against its own pair's columns only,
+ * so the result of pair k is that of skh_sinkhorn_divergence on (alpha_k,
+ * beta_k) with the same scale list.  The scale list is shared: its largest
+ * scale is params.diameter, or the diagonal of the joint bounding box of all
+ * points (an upper bound of every pair's distances); converged mode tests the
+ * marginal error summed over all pairs.  The packing centres all points on one
+ * midpoint (C is translation invariant; pairs far apart lose FP32 digits).
+ * x_off, y_off: host arrays of K + 1 nondecreasing offsets from 0, every pair
+ * at least one point on each side.  S_out: host array of K values of eq. (6).
+ * f, g, p, q: as for skh_sinkhorn_divergence over the concatenated points
+ * (fixed, init allowed).  Dense FP32 with p = 2 only (SKH_EINVAL otherwise).
+ */
+int skh_sinkhorn_divergence_batched(skh_ctx *ctx, const float *x, const float *a,
+                                    const int64_t *x_off, const float *y, const float *b,
+                                    const int64_t *y_off, int32_t K, int32_t d,
+                                    const skh_params *params, double *S_out, float *f, float *g,
+                                    float *p, float *q, skh_stats *stats);
+
+/*
  * The largest scale of the Algorithm's list for the pair (x, y): the diagonal
  * of their joint bounding box (an upper bound of max |x_i - y_j|, the
  * diameter of the parameter lines).  *out is a host double.  Synchronises.

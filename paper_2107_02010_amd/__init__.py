@@ -10,6 +10,7 @@ every arithmetic step runs in the library.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import math
 import threading
 
@@ -19,7 +20,7 @@ from . import _lib
 from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT, SKH_FIX_P, SKH_FIX_Q, SKH_FIX_CROSS  # noqa: F401
 
 __all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "gradients",
-           "label_transfer",
+           "label_transfer", "sinkhorn_divergence_batched",
            "diameter",
            "self_potential",
            "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
@@ -218,6 +219,61 @@ def label_transfer(x, a, y, b, labels, n_labels: int, blur: float = 1.0, reach=2
                                         _ptr(lab), _ptr(score), ctypes.byref(st))
     _lib.check(rc, ctx, allow_not_converged=True)
     return (lab, score, st.as_dict()) if stats else (lab, score)
+
+
+def sinkhorn_divergence_batched(xs, as_, ys, bs, blur: float = 0.05, reach=None,
+                                scaling: float = 0.9, diameter=None, extra_iters: int = 0,
+                                tol: float = 0.0, max_iters: int = 1000, check_every: int = 5,
+                                init=None, fixed: int = 0, potentials: bool = False,
+                                timing: bool = False):
+    """S_eps(alpha_k, beta_k) for K independent pairs in one solve (four softmin launches per
+    iteration for all pairs; dense FP32, p = 2).  xs, as_, ys, bs: lists of K CUDA tensors.
+    The scale list is shared (largest scale: diameter, else the bounding-box diagonal of all
+    points).  init: optional (f, g, p, q) over the concatenated points; fixed as for
+    sinkhorn_divergence.  Returns the list of K values, with potentials=True also the
+    per-pair dual vectors (lists) and the stats."""
+    K = len(xs)
+    if not (K >= 1 and len(as_) == K and len(ys) == K and len(bs) == K):
+        raise ValueError("xs, as_, ys, bs must be lists of the same length >= 1")
+    xs = [_as_points(t, "x") for t in xs]
+    ys = [_as_points(t, "y") for t in ys]
+    d = xs[0].shape[1]
+    if any(t.shape[1] != d for t in xs + ys):
+        raise ValueError("every cloud must have the same dimension")
+    dev = xs[0].device
+    xn = [t.shape[0] for t in xs]
+    yn = [t.shape[0] for t in ys]
+    x = torch.cat(xs).contiguous()
+    y = torch.cat(ys).contiguous()
+    a = torch.cat([_as_vec(w, k, "a", dev) for w, k in zip(as_, xn)]).contiguous()
+    b = torch.cat([_as_vec(w, k, "b", dev) for w, k in zip(bs, yn)]).contiguous()
+    n, m = x.shape[0], y.shape[0]
+    xo = (ctypes.c_int64 * (K + 1))(*([0] + list(itertools.accumulate(xn))))
+    yo = (ctypes.c_int64 * (K + 1))(*([0] + list(itertools.accumulate(yn))))
+    P = _solver_params(blur, reach, scaling, diameter, extra_iters, tol, max_iters, check_every,
+                       "fp32", timing, False, 0.0, 20.0, 0, 10)
+    P.fixed = int(fixed)
+    if fixed and init is None:
+        raise ValueError("fixed dual vectors are passed through init=(f, g, p, q)")
+    if init is not None:
+        f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in
+                      zip(init, (n, m, n, m), ("f", "g", "p", "q")))
+        P.init = _lib.SKH_INIT_GIVEN
+    else:
+        f, g, p, q = (torch.empty(k, dtype=torch.float32, device=dev) for k in (n, m, n, m))
+    S = (ctypes.c_double * K)()
+    st = _lib.SkhStats()
+    ctx = _Ctx.get(dev)
+    rc = _lib.load().skh_sinkhorn_divergence_batched(ctx, _ptr(x), _ptr(a), xo, _ptr(y), _ptr(b),
+                                                     yo, K, d, ctypes.byref(P), S, _ptr(f),
+                                                     _ptr(g), _ptr(p), _ptr(q), ctypes.byref(st))
+    _lib.check(rc, ctx, allow_not_converged=True)
+    vals = list(S)
+    if not potentials:
+        return vals
+    pot = dict(f=list(torch.split(f, xn)), g=list(torch.split(g, yn)),
+               p=list(torch.split(p, xn)), q=list(torch.split(q, yn)))
+    return vals, pot, st.as_dict()
 
 
 def diameter(x, y) -> float:

@@ -80,6 +80,10 @@ SIGNATURES = {
     "skh_sinkhorn_divergence": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32,
                                          ctypes.POINTER(SkhParams), ctypes.POINTER(_c_d), _c_vp,
                                          _c_vp, _c_vp, _c_vp, ctypes.POINTER(SkhStats)]),
+    "skh_sinkhorn_divergence_batched": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                                 _c_i32, _c_i32, ctypes.POINTER(SkhParams),
+                                                 _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                                 ctypes.POINTER(SkhStats)]),
     "skh_plan_apply": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp,
                                 _c_vp, _c_d, _c_vp, _c_i32, _c_i32, _c_vp, _c_vp]),
     "skh_grad_x": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp,

@@ -283,10 +283,45 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     return SKH_OK;
 }
 
+// Independent problems solved together (block-diagonal softmins): pair k owns the
+// points [x_off[k], x_off[k+1]) of x and [y_off[k], y_off[k+1]) of y (host offsets).
+struct Segments {
+    int K;
+    const int64_t *x_off, *y_off;
+    double *S;  // host, K values of eq. (6)
+};
+
+static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                 const float *b, int64_t m, int32_t d, const skh_params *params, double *S_out,
+                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg);
+
 int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_t n,
                             const float *y, const float *b, int64_t m, int32_t d,
                             const skh_params *params, double *S_out, float *f, float *g, float *p,
                             float *q, skh_stats *stats) {
+    return solve(ctx, x, a, n, y, b, m, d, params, S_out, f, g, p, q, stats, nullptr);
+}
+
+int skh_sinkhorn_divergence_batched(skh_ctx *ctx, const float *x, const float *a,
+                                    const int64_t *x_off, const float *y, const float *b,
+                                    const int64_t *y_off, int32_t K, int32_t d,
+                                    const skh_params *params, double *S_out, float *f, float *g,
+                                    float *p, float *q, skh_stats *stats) {
+    if (!ctx) return SKH_EINVAL;
+    if (!x_off || !y_off || !S_out) return fail(ctx, SKH_EINVAL, "NULL argument");
+    if (K < 1) return fail(ctx, SKH_EINVAL, "K must be >= 1");
+    if (x_off[0] != 0 || y_off[0] != 0) return fail(ctx, SKH_EINVAL, "offsets must start at 0");
+    for (int k = 0; k < K; ++k)
+        if (x_off[k + 1] <= x_off[k] || y_off[k + 1] <= y_off[k])
+            return fail(ctx, SKH_EINVAL, "every pair needs at least one point on each side");
+    const Segments seg{K, x_off, y_off, S_out};
+    double S = 0.0;
+    return solve(ctx, x, a, x_off[K], y, b, y_off[K], d, params, &S, f, g, p, q, stats, &seg);
+}
+
+static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                 const float *b, int64_t m, int32_t d, const skh_params *params, double *S_out,
+                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg) {
     if (!ctx) return SKH_EINVAL;
     const auto t_start = std::chrono::steady_clock::now();
     if (!x || !a || !y || !b || !params) return fail(ctx, SKH_EINVAL, "NULL argument");
@@ -335,6 +370,24 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
         return fail(ctx, SKH_EINVAL, "cost_p != 2 runs on the dense FP32 path only");
     auto powp = [pc](double v) { return pc == 2.0 ? v * v : std::pow(v, pc); };
     const double rho = balanced ? 0.0 : powp(P.reach);
+    if (seg && (split || ms || pc != 2.0))
+        return fail(ctx, SKH_EINVAL, "batched problems run on the dense FP32 path with p = 2");
+    // batched: row tiles of each pair against that pair's column range, per problem
+    // (0: rows x / cols x, 1: y / y, 2: y / x, 3: x / y)
+    std::vector<int4> seg_tiles[4];
+    std::vector<int2> seg_ranges[4];
+    if (seg) {
+        const int64_t *ro[4] = {seg->x_off, seg->y_off, seg->y_off, seg->x_off};
+        const int64_t *co[4] = {seg->x_off, seg->y_off, seg->x_off, seg->y_off};
+        for (int j = 0; j < 4; ++j) {
+            for (int k = 0; k < seg->K; ++k) {
+                for (int64_t r = ro[j][k]; r < ro[j][k + 1]; r += kRowTile)
+                    seg_tiles[j].push_back(
+                        make_int4((int)r, (int)std::min<int64_t>(r + kRowTile, ro[j][k + 1]), k, 0));
+                seg_ranges[j].push_back(make_int2((int)co[j][k], (int)co[j][k + 1]));
+            }
+        }
+    }
 
     DeviceGuard guard(ctx->device);
     hipStream_t s = ctx->stream;
@@ -346,6 +399,11 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     double *pmass, *mass;
     int *pbad, *bad, *wbad;
     Clustered cx, cy;
+    int4 *seg_dtiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    int2 *seg_dranges[4] = {nullptr, nullptr, nullptr, nullptr};
+    int *seg_ones = nullptr;
+    int64_t *seg_xoff = nullptr, *seg_yoff = nullptr;
+    double *seg_out = nullptr;
     for (int pass = 0; pass < 2; ++pass) {
         Carver c(pass ? ctx->ws[0] : nullptr);
         Xp = c.take<float>((size_t)n * kp);
@@ -366,6 +424,16 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
             cx.carve(c, (int)n, kp, P.n_clusters);
             cy.carve(c, (int)m, kp, P.n_clusters);
         }
+        if (seg) {
+            for (int j = 0; j < 4; ++j) {
+                seg_dtiles[j] = c.take<int4>(seg_tiles[j].size());
+                seg_dranges[j] = c.take<int2>(seg_ranges[j].size());
+            }
+            seg_ones = c.take<int>(seg->K);
+            seg_xoff = c.take<int64_t>(seg->K + 1);
+            seg_yoff = c.take<int64_t>(seg->K + 1);
+            seg_out = c.take<double>(seg->K);
+        }
         if (ms) {
             dist[0] = c.take<float>((size_t)cx.k * cx.k);
             dist[1] = c.take<float>((size_t)cy.k * cy.k);
@@ -381,6 +449,22 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
     SKH_HIP(skh::launch_bbox_partial(y, b, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
                                      pmass + nbx, pbad + 2 * nbx, s));
     SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nbx, nby, d, lohi, mass, bad, s));
+    std::vector<int> seg_one_h;
+    if (seg) {
+        for (int j = 0; j < 4; ++j) {
+            SKH_HIP(hipMemcpyAsync(seg_dtiles[j], seg_tiles[j].data(),
+                                   seg_tiles[j].size() * sizeof(int4), hipMemcpyHostToDevice, s));
+            SKH_HIP(hipMemcpyAsync(seg_dranges[j], seg_ranges[j].data(),
+                                   seg_ranges[j].size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        }
+        seg_one_h.assign(seg->K, 1);
+        SKH_HIP(hipMemcpyAsync(seg_ones, seg_one_h.data(), seg->K * sizeof(int),
+                               hipMemcpyHostToDevice, s));
+        SKH_HIP(hipMemcpyAsync(seg_xoff, seg->x_off, (seg->K + 1) * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+        SKH_HIP(hipMemcpyAsync(seg_yoff, seg->y_off, (seg->K + 1) * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+    }
     char *hb = static_cast<char *>(ctx->host);
     SKH_HIP(hipMemcpyAsync(hb, lohi, 128 * sizeof(float), hipMemcpyDeviceToHost, s));
     SKH_HIP(hipMemcpyAsync(hb + 512, mass, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -528,6 +612,13 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
             batch.job[k].range_cap = colc[k]->k / 2 + 2;
             batch.job[k].tiles = rowc[k]->tiles;  // marks block-sparse mode for planning
         }
+        if (seg) {  // one range per pair: its own columns
+            batch.job[k].n_tiles = skip_job[k] ? 0 : (int)seg_tiles[k].size();
+            batch.job[k].range_cap = 1;
+            batch.job[k].tiles = seg_dtiles[k];
+            batch.job[k].ranges = seg_dranges[k];
+            batch.job[k].range_count = seg_ones;
+        }
     }
     const int wgs = skh::plan_softmin_batch(batch, target_wgs(ctx));
     const int fbx = skh::finish_blocks(nn), fby = skh::finish_blocks(mm);
@@ -617,9 +708,18 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
 
     // ---- Coarse phase: the loop on the K-means centres, then the jump ----
     double pairs = 0.0, dense_pairs = 0.0;
-    const double pairs_per_iter = (skip_job[0] ? 0.0 : (double)n * n) +
-                                  (skip_job[1] ? 0.0 : (double)m * m) +
-                                  (skip_job[2] ? 0.0 : 2.0 * (double)n * m);
+    double pairs_per_iter = (skip_job[0] ? 0.0 : (double)n * n) +
+                            (skip_job[1] ? 0.0 : (double)m * m) +
+                            (skip_job[2] ? 0.0 : 2.0 * (double)n * m);
+    if (seg) {
+        pairs_per_iter = 0.0;
+        for (int k = 0; k < seg->K; ++k) {
+            const double nk = (double)(seg->x_off[k + 1] - seg->x_off[k]);
+            const double mk = (double)(seg->y_off[k + 1] - seg->y_off[k]);
+            pairs_per_iter += (skip_job[0] ? 0.0 : nk * nk) + (skip_job[1] ? 0.0 : mk * mk) +
+                              (skip_job[2] ? 0.0 : 2.0 * nk * mk);
+        }
+    }
     if (ms && t_jump > 0) {
         float *Fc = cpot[0], *Gc = cpot[1], *Pc = cpot[2], *Qc = cpot[3];
         for (int k = 0; k < 4; ++k) SKH_HIP(hipMemsetAsync(cpot[k], 0, (k % 2 ? ky : kx) * sizeof(float), s));
@@ -852,12 +952,23 @@ int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_
             if (outs[k])
                 SKH_HIP(skh::launch_unpermute(pot[k], cl[k]->perm_pad, cl[k]->n_pad, outs[k], s));
     }
+    std::vector<double> seg_S;
+    if (seg) {
+        SKH_HIP(skh::launch_divergence_segments(wX, F, Pp, seg_xoff, wY, G, Q, seg_yoff, seg->K, rho,
+                                                balanced ? 1 : 0, seg_out, s));
+        seg_S.resize(seg->K);
+        SKH_HIP(hipMemcpyAsync(seg_S.data(), seg_out, seg->K * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
     SKH_HIP(hipStreamSynchronize(s));
     double S = *reinterpret_cast<const double *>(hb + 1024);
     if (ms) pairs += (double)*reinterpret_cast<const unsigned long long *>(hb + 1088);
     const double eps_blur = powp(P.blur);
     if (!balanced) S = -(rho + 0.5 * eps_blur) * S;
     if (S_out) *S_out = S;
+    if (seg)
+        for (int k = 0; k < seg->K; ++k)
+            seg->S[k] = balanced ? seg_S[k] : -(rho + 0.5 * eps_blur) * seg_S[k];
     double ms_softmin = 0.0;
     if (P.timing) {
         for (int k = 0; k < launches; ++k) {

@@ -371,4 +371,44 @@ hipError_t launch_divergence_terms(const float *a, const float *f, const float *
     return hipGetLastError();
 }
 
+// eq. (6) per pair of a batched solve: one workgroup per pair k sums its x points
+// [xo[k], xo[k+1]) and y points [yo[k], yo[k+1]) in FP64 (fixed order per thread, then a
+// tree); out[k] is the bracket of eq. (6) (balanced: the value itself).
+__global__ __launch_bounds__(kThreads) void k_divergence_segments(
+    const float *__restrict__ a, const float *__restrict__ f, const float *__restrict__ p,
+    const int64_t *__restrict__ xo, const float *__restrict__ b, const float *__restrict__ g,
+    const float *__restrict__ q, const int64_t *__restrict__ yo, double rho, int balanced,
+    double *__restrict__ out) {
+    __shared__ double red[kThreads];
+    const int k = blockIdx.x;
+    double v = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int64_t lo = side ? yo[k] : xo[k], hi = side ? yo[k + 1] : xo[k + 1];
+        const float *w = side ? b : a, *pc = side ? g : f, *ps = side ? q : p;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+            const double wi = w[i];
+            if (wi > 0.0) {
+                const double c = pc[i], t = ps[i];
+                v += balanced ? wi * (c - t) : wi * exp(-t / rho) * expm1(-(c - t) / rho);
+            }
+        }
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+}
+
+hipError_t launch_divergence_segments(const float *a, const float *f, const float *p,
+                                      const int64_t *xo, const float *b, const float *g,
+                                      const float *q, const int64_t *yo, int K, double rho,
+                                      int balanced, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_divergence_segments, dim3(K), dim3(kThreads), 0, s, a, f, p, xo, b, g, q,
+                       yo, rho, balanced, out);
+    return hipGetLastError();
+}
+
 }  // namespace skh

@@ -208,6 +208,10 @@ hipError_t launch_divergence_terms(const float *a, const float *f, const float *
                                    const float *b, const float *g, const float *q, int64_t m,
                                    double rho, int balanced, double *part, int *nb_out,
                                    hipStream_t s);
+hipError_t launch_divergence_segments(const float *a, const float *f, const float *p,
+                                      const int64_t *xo, const float *b, const float *g,
+                                      const float *q, const int64_t *yo, int K, double rho,
+                                      int balanced, double *out, hipStream_t s);
 
 // ---- Learned warm start (set encoder over K-means cluster tokens) ----
 constexpr int kWsIn = 64;      // token features
