@@ -24,6 +24,7 @@ broadcast are inside the timed region).
 --workload labels200k: label transfer from a 200k-fibre labelled atlas to a 200k-fibre
 subject (random fibre directions, 1 % aberrant fibres) with flip augmentation.
 --workload pcost200k: full solve with the cost |x - y| (p = 1) on 200k x 200k 3-D clouds.
+--workload barycenter10: one barycenter descent step over 10 density maps, 200k support.
 
 Prints one JSON line:
   value       = softmin point pairs evaluated / wall time of the timed steps (Gpair/s)
@@ -322,6 +323,42 @@ def bench_pcost(args, skh, synth):
     return 0
 
 
+def bench_barycenter(args, skh, synth):
+    """One Wasserstein-barycenter descent step (Section 3, track density atlas): 10 density
+    maps on a 128^3 grid (~200k-270k voxels each), a 200k-point support, blur 1 voxel,
+    balanced; the maps' cross loops as one batched solve against one solve per map."""
+    import torch
+    from paper_2107_02010_amd.barycenter import Barycenter
+    print("[bench] generating 10 density maps (128^3)", file=sys.stderr, flush=True)
+    maps = synth.density_maps(10, seed=11)
+    x0, a = synth.barycenter_support(maps, 200_000, seed=12)
+    ym = [(torch.as_tensor(c).cuda(), torch.as_tensor(w).cuda()) for c, w in maps]
+    X, A = torch.as_tensor(x0).cuda(), torch.as_tensor(a).cuda()
+    res = {}
+    for batched in (True, False):
+        B = Barycenter(A, ym, blur=1.0, scaling=0.9, x0=X, batched=batched)
+        B._setup(X)  # the maps' self vectors: once for the whole descent, outside the step
+        dt, (x1, S, _) = _timed(lambda: B.step(X), args.steps, args.warmup)
+        res["batched" if batched else "per_map"] = {"s_per_step": round(dt, 4), "mean_S": S}
+        print(f"[bench] barycenter step ({'batched' if batched else 'per map'}): {dt:.3f} s",
+              file=sys.stderr, flush=True)
+    m_total = sum(len(c) for c, _ in maps)
+    out = {"metric": "time per barycenter step, 10 density maps (128^3), 200k support points",
+           "value": res["batched"]["s_per_step"], "unit": "s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(res["batched"]["s_per_step"] * 1e3, 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"Wasserstein barycenter step, 10 maps ({m_total} voxels in "
+                                  "total), 200000 support points, blur 1 voxel, reach none, "
+                                  "scaling 0.9; self loop of the support per step, cross loops "
+                                  "of all maps, 10 gradients"},
+           "batched": res["batched"], "per_map": res["per_map"],
+           "speedup_batched": round(res["per_map"]["s_per_step"] / res["batched"]["s_per_step"], 3)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,7 +367,7 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
     ap.add_argument("--workload", default="fibers200k",
                     choices=["fibers200k", "multiscale1m", "grad200k", "labels200k",
-                             "pcost200k"])
+                             "pcost200k", "barycenter10"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison solve")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
@@ -368,6 +405,8 @@ def main() -> int:
         return bench_labels(args, skh, synth)
     if args.workload == "pcost200k":
         return bench_pcost(args, skh, synth)
+    if args.workload == "barycenter10":
+        return bench_barycenter(args, skh, synth)
     print(f"[bench] generating {args.n} x {args.n} fibre clouds", file=sys.stderr, flush=True)
     x, a, y, b = synth.fiber_pair(args.n, args.bundles, seed=0)
     dev = torch.device("cuda:0")

@@ -15,22 +15,28 @@ list for all maps a step needs:
     fixed,
 and gives the same S_k, f_k, g_k as K full solves with that scale list.  The
 common largest scale is the largest joint bounding-box diagonal over the maps
-at the start (any upper bound of the distances is a valid first scale).
+at the start (any upper bound of the distances is a valid first scale).  In
+FP32 the K cross loops run as one batched solve: every iteration is one launch
+over all maps (row tiles of each map's copy of the support against that map's
+columns only).
 """
 from __future__ import annotations
 
 import torch
 
-from . import SKH_FIX_P, SKH_FIX_Q, diameter, grad_x, self_potential, sinkhorn_divergence
+from . import (SKH_FIX_P, SKH_FIX_Q, diameter, grad_x, self_potential, sinkhorn_divergence,
+               sinkhorn_divergence_batched)
 
 
 class Barycenter:
     """Gradient descent on the support of alpha against K fixed maps."""
 
     def __init__(self, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
-                 lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0, x0=None):
+                 lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0, x0=None,
+                 batched: bool = True):
         self.a = a
         self.maps = maps
+        self.batched = batched and precision == "fp32"
         self.kw = dict(blur=blur, reach=reach, scaling=scaling, precision=precision,
                        extra_iters=extra_iters)
         self.lr = lr
@@ -50,6 +56,22 @@ class Barycenter:
         grad = torch.zeros_like(x)
         total = 0.0
         pots = []
+        if self.batched:
+            K, n = len(self.maps), x.shape[0]
+            m = sum(y.shape[0] for y, _ in self.maps)
+            init = (torch.zeros(K * n, dtype=torch.float32, device=x.device),
+                    torch.zeros(m, dtype=torch.float32, device=x.device), p.repeat(K),
+                    torch.cat(self.q))
+            kw = {k: v for k, v in self.kw.items() if k != "precision"}
+            S, pot, _ = sinkhorn_divergence_batched(
+                [x] * K, [self.a] * K, [y for y, _ in self.maps], [b for _, b in self.maps],
+                diameter=self.d, init=init, fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True, **kw)
+            for k, (y, b) in enumerate(self.maps):
+                pk = dict(f=pot["f"][k], g=pot["g"][k], p=pot["p"][k], q=pot["q"][k])
+                grad += grad_x(x, self.a, y, b, pk["f"], pk["g"], pk["p"], self.kw["blur"])
+                pots.append(pk)
+            grad /= K
+            return x - self.lr * grad / self.a[:, None], sum(S) / K, pots
         for (y, b), q in zip(self.maps, self.q):
             zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
             zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
@@ -65,12 +87,12 @@ class Barycenter:
 
 def barycenter_step(x, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
                     lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0,
-                    diameter_=None):
+                    diameter_=None, batched: bool = True):
     """One gradient step with the scale list from diameter_ (None: the largest joint
     bounding-box diagonal of x with each map).  maps: list of (y_k, b_k) CUDA tensors.
 
     Returns (new x, mean S, list of per-map potentials dicts)."""
-    B = Barycenter(a, maps, blur, reach, scaling, lr, precision, extra_iters)
+    B = Barycenter(a, maps, blur, reach, scaling, lr, precision, extra_iters, batched=batched)
     B.d = diameter_
     return B.step(x)
 

@@ -100,3 +100,22 @@ def test_fixed_loops_argument_checks():
     with pytest.raises(skh.SkhError):
         skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=skh.SKH_FIX_P,
                                 multiscale=True)
+
+
+def test_batched_step_matches_per_map_step():
+    # one launch per iteration for all maps against one solve per map: same S_k and the
+    # same step up to FP32 summation order
+    from paper_2107_02010_amd.barycenter import barycenter_step
+    maps = synth.density_maps(3, seed=5, grid=24, n_tubes=3, nonzero=(500, 900),
+                              sigma=(1.0, 2.0), jitter=1.5)
+    x0, a = synth.barycenter_support(maps, 700, seed=6)
+    ym = [(cuda(c), cuda(w)) for c, w in maps]
+    note("barycenter batched vs per-map step")
+    x1, S1, p1 = barycenter_step(cuda(x0), cuda(a), ym, blur=1.0, scaling=0.7, batched=True)
+    x2, S2, p2 = barycenter_step(cuda(x0), cuda(a), ym, blur=1.0, scaling=0.7, batched=False)
+    assert S1 == pytest.approx(S2, rel=1e-5)
+    np.testing.assert_allclose(host(x1), host(x2), atol=1e-4 * 24)
+    for u, v in zip(p1, p2):
+        fu, fv = host(u["f"]), host(v["f"])
+        np.testing.assert_allclose(fu - fu.mean(), fv - fv.mean(),
+                                   atol=1e-4 * max(1.0, np.abs(fv).max()))
