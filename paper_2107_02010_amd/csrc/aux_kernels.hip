@@ -35,21 +35,26 @@ int bbox_blocks(int64_t n) { return (int)((n + kBBoxSeg - 1) / kBBoxSeg); }
 
 // Block b covers points [b*SEG, (b+1)*SEG).  pbad[2b] counts non-finite
 // coordinates, pbad[2b+1] negative, NaN or infinite weights.
+// The block reads its points' coordinates as one contiguous run: thread t < S
+// (S = the largest multiple of d not above the block size) takes the elements
+// t, t + S, t + 2S, ... of the run, all of coordinate t % d; the per-coordinate
+// extremes are then combined over the threads t % d = k.
 __global__ __launch_bounds__(kThreads) void k_bbox_partial(const float *__restrict__ x,
                                                            const float *__restrict__ w, int64_t n,
                                                            int d, float *plo, float *phi,
                                                            double *pmass, int *pbad) {
-    __shared__ float slo[4][64], shi[4][64];
+    __shared__ float tlo[kThreads], thi[kThreads];
     __shared__ double sm[4];
     __shared__ int sb[4][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t beg = (int64_t)blockIdx.x * kBBoxSeg;
     const int64_t end = min(n, beg + kBBoxSeg);
+    const int S = (kThreads / d) * d;
     int badc = 0, badw = 0;
-    for (int k = 0; k < d; ++k) {
-        float lo = finf(), hi = -finf();
-        for (int64_t i = beg + tid; i < end; i += kThreads) {
-            const float v = x[i * d + k];
+    float lo = finf(), hi = -finf();
+    if (tid < S) {
+        for (int64_t e = beg * d + tid; e < end * d; e += S) {
+            const float v = x[e];
             if (!isfinite(v)) {
                 ++badc;
             } else {
@@ -57,13 +62,9 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const float *__restri
                 hi = fmaxf(hi, v);
             }
         }
-        lo = wave_min(lo);
-        hi = wave_max(hi);
-        if (lane == 0) {
-            slo[wave][k] = lo;
-            shi[wave][k] = hi;
-        }
     }
+    tlo[tid] = lo;
+    thi[tid] = hi;
     double ms = 0.0;
     if (w) {
         for (int64_t i = beg + tid; i < end; i += kThreads) {
@@ -84,10 +85,13 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const float *__restri
     }
     __syncthreads();
     if (tid < d) {
-        float lo = fminf(fminf(slo[0][tid], slo[1][tid]), fminf(slo[2][tid], slo[3][tid]));
-        float hi = fmaxf(fmaxf(shi[0][tid], shi[1][tid]), fmaxf(shi[2][tid], shi[3][tid]));
-        plo[(size_t)blockIdx.x * 64 + tid] = lo;
-        phi[(size_t)blockIdx.x * 64 + tid] = hi;
+        float l = finf(), h = -finf();
+        for (int t = tid; t < S; t += d) {
+            l = fminf(l, tlo[t]);
+            h = fmaxf(h, thi[t]);
+        }
+        plo[(size_t)blockIdx.x * 64 + tid] = l;
+        phi[(size_t)blockIdx.x * 64 + tid] = h;
     }
     if (tid == 0) {
         pmass[blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
@@ -152,32 +156,38 @@ hipError_t launch_bbox_final(const float *plo, const float *phi, const double *p
     return hipGetLastError();
 }
 
+// kp consecutive lanes share a point (kp divides the wave), one coordinate each, so the
+// loads and stores of a wave are contiguous; the FP64 half norm is reduced across them.
 __global__ __launch_bounds__(kThreads) void k_pack(const float *__restrict__ x,
                                                    const float *__restrict__ w, int64_t n, int d,
                                                    int kp, const float *__restrict__ centre,
                                                    float *__restrict__ P, float *__restrict__ hn,
                                                    float *__restrict__ lw) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int k = 0; k < kp; ++k) {
-        float v = 0.0f;
-        if (k < d) v = (float)((double)x[i * d + k] - (double)centre[k]);
-        P[i * kp + k] = v;
-        s += (double)v * (double)v;
-    }
-    hn[i] = (float)(0.5 * s);
-    if (lw) {
-        const float wi = w ? w[i] : 1.0f;
-        lw[i] = wi > 0.0f ? (float)log((double)wi) : -finf();
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t i = e / kp;
+    const int k = (int)(e - i * kp);
+    const bool live = i < n;
+    const int64_t ic = live ? i : n - 1;  // every lane takes part in the reduction
+    float v = 0.0f;
+    if (k < d) v = (float)((double)x[ic * d + k] - (double)centre[k]);
+    double s = (double)v * (double)v;
+    for (int o = kp / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (!live) return;
+    P[e] = v;
+    if (k == 0) {
+        hn[i] = (float)(0.5 * s);
+        if (lw) {
+            const float wi = w ? w[i] : 1.0f;
+            lw[i] = wi > 0.0f ? (float)log((double)wi) : -finf();
+        }
     }
 }
 
 hipError_t launch_pack(const float *x, const float *w, int64_t n, int d, int kp,
                        const float *centre, float *P, float *hn, float *lw, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, x, w, n, d, kp, centre, P, hn, lw);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n * kp + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, x, w, n, d, kp, centre, P, hn, lw);
     return hipGetLastError();
 }
 

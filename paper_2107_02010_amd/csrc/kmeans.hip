@@ -205,20 +205,23 @@ hipError_t launch_exclusive_scan(const int *in, int64_t len, int *sums, int *out
 // [off[c], off[c+1]) of perm), FP64 accumulation in a fixed order.  Members with
 // zero weight do not move the centre; a cluster with no mass keeps its centre.
 // Also writes the cluster mass (FP32 of the FP64 sum).
+constexpr int kCU = 1024;  // threads of the centroid update: 16 waves walk one cluster
+
 template <int KP>
-__global__ __launch_bounds__(kT) void k_centroid_update(const float *__restrict__ X,
-                                                        const float *__restrict__ w,
-                                                        const int *__restrict__ perm,
-                                                        const int *__restrict__ off,
-                                                        float *__restrict__ C,
-                                                        float *__restrict__ cmass) {
-    __shared__ double sh[4][KP];
-    __shared__ double shm[4];
+__global__ __launch_bounds__(kCU) void k_centroid_update(const float *__restrict__ X,
+                                                         const float *__restrict__ w,
+                                                         const int *__restrict__ perm,
+                                                         const int *__restrict__ off,
+                                                         float *__restrict__ C,
+                                                         float *__restrict__ cmass) {
+    constexpr int NW = kCU / 64;
+    __shared__ double sh[NW][KP];
+    __shared__ double shm[NW];
     const int c = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int beg = off[c], end = off[c + 1];
     double acc = 0.0, m = 0.0;
-    for (int p = beg + wave; p < end; p += 4) {
+    for (int p = beg + wave; p < end; p += NW) {
         const int i = perm[p];
         const double wi = w ? (double)w[i] : 1.0;
         if (lane < KP) acc += wi * (double)X[(size_t)i * KP + lane];
@@ -227,10 +230,14 @@ __global__ __launch_bounds__(kT) void k_centroid_update(const float *__restrict_
     if (lane < KP) sh[wave][lane] = acc;
     if (lane == 0) shm[wave] = m;
     __syncthreads();
-    if (threadIdx.x < KP) {
+    if (threadIdx.x < KP) {  // the waves' partial sums in a fixed order
         const int d = threadIdx.x;
-        const double mass = ((shm[0] + shm[1]) + shm[2]) + shm[3];
-        const double sum = ((sh[0][d] + sh[1][d]) + sh[2][d]) + sh[3][d];
+        double mass = 0.0, sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            mass += shm[q];
+            sum += sh[q][d];
+        }
         if (mass > 0.0) C[(size_t)c * KP + d] = (float)(sum / mass);
         if (d == 0 && cmass) cmass[c] = (float)mass;
     }
@@ -321,27 +328,43 @@ __global__ __launch_bounds__(kT) void k_pack_padded(
     float *__restrict__ Xf, __hip_bfloat16 *__restrict__ Yhi0, __hip_bfloat16 *__restrict__ Yhi1,
     __hip_bfloat16 *__restrict__ Ylo, float *__restrict__ hn, float *__restrict__ lw,
     float *__restrict__ wp) {
-    const int p = blockIdx.x * kT + threadIdx.x;
-    if (p >= n_pad) return;
-    const int i = perm_pad[p];
-    const int c = blk_cluster[p >> 5];
+    // KP / 4 consecutive lanes share a point (4 coordinates each), so every load and
+    // store of a wave covers whole contiguous rows
+    constexpr int G = KP / 4;
+    constexpr int PPB = kT / G;  // points per block
+    const int t = threadIdx.x % G;
+    const int p = blockIdx.x * PPB + threadIdx.x / G;
+    const bool live = p < n_pad;
+    const int pc = live ? p : n_pad - 1;  // every lane takes part in the reduction
+    const int i = perm_pad[pc];
+    const int c = blk_cluster[pc >> 5];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i >= 0) v = *reinterpret_cast<const float4 *>(X + (size_t)i * KP + 4 * t);
+    const float4 cc = *reinterpret_cast<const float4 *>(C + (size_t)c * KP + 4 * t);
+    const float vv[4] = {v.x, v.y, v.z, v.w}, cv[4] = {cc.x, cc.y, cc.z, cc.w};
+    __hip_bfloat16 hi[4], lo[4];
     double s = 0.0;
-    for (int d = 0; d < KP; ++d) {
-        const float v = i >= 0 ? X[(size_t)i * KP + d] : 0.0f;
-        Xf[(size_t)p * KP + d] = v;
-        s += (double)v * (double)v;
-        const float dv = i >= 0 ? v - C[(size_t)c * KP + d] : 0.0f;
-        __hip_bfloat16 hi = __float2bfloat16(dv);
-        const __hip_bfloat16 lo = __float2bfloat16(dv - __bfloat162float(hi));
-        if (d == KP - 1) hi = __float2bfloat16(1.0f);
-        Yhi0[(size_t)p * KP + d] = hi;
-        Yhi1[(size_t)p * KP + d] = hi;
-        Ylo[(size_t)p * KP + d] = lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s += (double)vv[e] * (double)vv[e];
+        const float dv = i >= 0 ? vv[e] - cv[e] : 0.0f;
+        hi[e] = __float2bfloat16(dv);
+        lo[e] = __float2bfloat16(dv - __bfloat162float(hi[e]));
+        if (4 * t + e == KP - 1) hi[e] = __float2bfloat16(1.0f);
     }
-    hn[p] = (float)(0.5 * s);
-    const float wi = i >= 0 ? (w ? w[i] : 1.0f) : 0.0f;
-    wp[p] = wi;
-    lw[p] = wi > 0.0f ? (float)log((double)wi) : -__builtin_huge_valf();
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (!live) return;
+    *reinterpret_cast<float4 *>(Xf + (size_t)p * KP + 4 * t) = v;
+    *reinterpret_cast<uint2 *>(Yhi0 + (size_t)p * KP + 4 * t) = *reinterpret_cast<const uint2 *>(hi);
+    *reinterpret_cast<uint2 *>(Yhi1 + (size_t)p * KP + 4 * t) = *reinterpret_cast<const uint2 *>(hi);
+    *reinterpret_cast<uint2 *>(Ylo + (size_t)p * KP + 4 * t) = *reinterpret_cast<const uint2 *>(lo);
+    if (t == 0) {
+        hn[p] = (float)(0.5 * s);
+        const float wi = i >= 0 ? (w ? w[i] : 1.0f) : 0.0f;
+        wp[p] = wi;
+        lw[p] = wi > 0.0f ? (float)log((double)wi) : -__builtin_huge_valf();
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_blk_centroids(const int *__restrict__ blk_cluster,
@@ -434,12 +457,12 @@ hipError_t run_kmeans(const float *X, const float *w, int n, int kp, int k, int 
                            off);
         // the last pass only sorts by the final centres (labels consistent with C)
         if (it < iters) {
-            SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C,
+            SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kCU), 0, s, X, w, perm, off, C,
                             cmass);
         }
     }
     // the coarse points are the weighted means of the final clusters, with their masses
-    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C, cmass);
+    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kCU), 0, s, X, w, perm, off, C, cmass);
     if (radius) SKH_KP_DISPATCH(kp, k_cluster_radius, dim3(k), dim3(kT), 0, s, X, perm, off, C, radius);
     *perm_out = perm;
     *off_out = off;
@@ -463,8 +486,10 @@ hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pa
                               const int *blk_cluster, const float *C, int n_pad, int kp, float *Xf,
                               __hip_bfloat16 *Yhi0, __hip_bfloat16 *Yhi1, __hip_bfloat16 *Ylo,
                               float *hn, float *lw, float *wp, hipStream_t s) {
-    SKH_KP_DISPATCH(kp, k_pack_padded, dim3(blocks(n_pad)), dim3(kT), 0, s, X, w, perm_pad,
-                    blk_cluster, C, n_pad, Xf, Yhi0, Yhi1, Ylo, hn, lw, wp);
+    if (n_pad == 0) return hipSuccess;
+    const int ppb = kT / (kp / 4);  // points per block
+    SKH_KP_DISPATCH(kp, k_pack_padded, dim3((n_pad + ppb - 1) / ppb), dim3(kT), 0, s, X, w,
+                    perm_pad, blk_cluster, C, n_pad, Xf, Yhi0, Yhi1, Ylo, hn, lw, wp);
     return hipGetLastError();
 }
 
@@ -541,7 +566,7 @@ hipError_t clusters_from_labels(const float *X, const float *w, int n, int kp, i
     int *perm, *off;
     e = sort_labels(n, k, ws, &perm, &off, s);
     if (e != hipSuccess) return e;
-    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kT), 0, s, X, w, perm, off, C, cmass);
+    SKH_KP_DISPATCH(kp, k_centroid_update, dim3(k), dim3(kCU), 0, s, X, w, perm, off, C, cmass);
     if (radius) SKH_KP_DISPATCH(kp, k_cluster_radius, dim3(k), dim3(kT), 0, s, X, perm, off, C, radius);
     *perm_out = perm;
     *off_out = off;
