@@ -703,3 +703,22 @@ def test_cost_p_strong_duality(reach):
     # eq. (6) equals eq. (5) through the duals
     S5 = oracle.divergence_eq5(x, a, y, b, r["f"], r["g"], r["p"], r["q"], blur, reach, pexp=1.0)
     assert S == pytest.approx(S5, rel=1e-9, abs=1e-12)
+
+
+def test_label_transfer_flip_copies_carry_the_fibre_weight():
+    # A palindromic fibre equals its flip, so the augmented subject holds every point twice
+    # at weight a_i: the same measure as the points once at 2 a_i.  Each copy's label is
+    # normalised by its own weight a_i, so Lab with flips = 2 Lab of the doubled subject.
+    P = 4
+    x0 = synth.fibers(30, 3, spine_seed=40, seed=45, points=P).astype(np.float64)
+    x = 0.5 * (x0 + oracle.flip_fibers(x0, P))  # palindromic
+    np.testing.assert_array_equal(oracle.flip_fibers(x, P), x)
+    y = synth.fibers(40, 3, spine_seed=40, seed=46, points=P)
+    ly = synth.fiber_labels(40, 3)
+    a, b = _u(30), _u(40)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.7, tol=1e-13, max_iters=100000)
+    lab_f, score_f, r1 = oracle.label_transfer(x, a, y, b, ly, 3, flip_points=P, **kw)
+    lab_2, score_2, r2 = oracle.label_transfer(x, 2 * a, y, b, ly, 3, **kw)
+    assert r1["converged"] and r2["converged"]
+    np.testing.assert_allclose(lab_f, 2 * lab_2, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(score_f, 2 * score_2, rtol=1e-8)
