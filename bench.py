@@ -141,8 +141,8 @@ def bench_multiscale(args, skh, synth):
     x, a, y, b = synth.fiber_pair(n, 200, seed=0)
     dev = torch.device("cuda:0")
     X, A, Y, B = (torch.as_tensor(v).to(dev) for v in (x, a, y, b))
-    kw = dict(blur=1.0, reach=20.0, scaling=0.9, tol=1e-4, check_every=5, max_iters=20000,
-              multiscale=True, potentials=True, timing=True)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.9, tol=1e-4, check_every=args.check_every,
+              max_iters=20000, multiscale=True, potentials=True, timing=True)
     res = {}
     for prec in ("fp32", "bf16x3"):
         agg = solve_steps(skh, X, A, Y, B, 1, args.warmup, f"multiscale {prec}", precision=prec, **kw)
@@ -186,7 +186,8 @@ def bench_multiscale(args, skh, synth):
         "data": "synthetic",
         "config": {"workload": f"fibre clouds n=m={n}, 60-D, 200 Bezier bundles, jitter 2 mm, "
                                "blur 1 mm, reach 20 mm, scaling 0.9, K-means sqrt(n) clusters, "
-                               "truncation theta 20, tolerance 1e-4"},
+                               f"truncation theta 20, tolerance 1e-4 checked every "
+                               f"{args.check_every} iterations"},
         "plain_fp32": plain, "bf16x3_cold": res["bf16x3"], "chosen_bf16x3_warm": chosen,
         "speedup_chosen_vs_plain": round(plain["time_to_S_s"] / chosen["time_to_S_s"], 3),
         "S_rel_diff": abs(chosen["S"] - plain["S"]) / abs(plain["S"]),
@@ -372,6 +373,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-every", type=int, default=5,
+                    help="multiscale1m: iterations between marginal-error checks at blur")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times), "
                          "to scale the HBM byte counters of a profiler")

@@ -291,9 +291,18 @@ struct Segments {
     double *S;  // host, K values of eq. (6)
 };
 
+// The cross plan applied to column values after a multiscale loop, over the kept
+// cluster blocks of the final potentials: out_i = (pi V)_i / a_i (eq. (4), eq. (7)).
+struct PostPlan {
+    const float *V;  // m x L, caller order (device)
+    int L;
+    float *out;      // n x L, caller order (device)
+};
+
 static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
                  const float *b, int64_t m, int32_t d, const skh_params *params, double *S_out,
-                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg);
+                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg,
+                 const PostPlan *pp = nullptr);
 
 int skh_sinkhorn_divergence(skh_ctx *ctx, const float *x, const float *a, int64_t n,
                             const float *y, const float *b, int64_t m, int32_t d,
@@ -321,7 +330,8 @@ int skh_sinkhorn_divergence_batched(skh_ctx *ctx, const float *x, const float *a
 
 static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
                  const float *b, int64_t m, int32_t d, const skh_params *params, double *S_out,
-                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg) {
+                 float *f, float *g, float *p, float *q, skh_stats *stats, const Segments *seg,
+                 const PostPlan *pp) {
     if (!ctx) return SKH_EINVAL;
     const auto t_start = std::chrono::steady_clock::now();
     if (!x || !a || !y || !b || !params) return fail(ctx, SKH_EINVAL, "NULL argument");
@@ -372,6 +382,9 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
     const double rho = balanced ? 0.0 : powp(P.reach);
     if (seg && (split || ms || pc != 2.0))
         return fail(ctx, SKH_EINVAL, "batched problems run on the dense FP32 path with p = 2");
+    const int pp_lp = pp ? skh::plan_value_width(pp->L) : 0;
+    if (pp && (!ms || pc != 2.0 || (P.fixed & SKH_FIX_CROSS) || pp->L < 1 || !pp_lp))
+        return fail(ctx, SKH_EINVAL, "post-solve plan: multiscale, p = 2, 1 <= L <= 64");
     // batched: row tiles of each pair against that pair's column range, per problem
     // (0: rows x / cols x, 1: y / y, 2: y / x, 3: x / y)
     std::vector<int4> seg_tiles[4];
@@ -650,6 +663,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
     int *rcount[4] = {nullptr, nullptr, nullptr, nullptr};
     float *cmax[4] = {nullptr, nullptr, nullptr, nullptr};  // f, g, p, q maxima per cluster
     unsigned long long *pairs_ctr = nullptr;
+    float *pp_V = nullptr, *pp_part = nullptr, *pp_out = nullptr;
     float *uc[4], *cpot[4], *ju[4];
     float2 *cpart[4], *jpart[4];
     double *cacc = nullptr;
@@ -671,6 +685,11 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
                 cmax[k] = c.take<float>(kk[k]);
             }
             pairs_ctr = c.take<unsigned long long>(1);
+            if (pp) {
+                pp_V = c.take<float>((size_t)cy.n_pad * pp->L);
+                pp_part = c.take<float>((size_t)cx.n_pad * (pp->L + 2));
+                pp_out = c.take<float>((size_t)cx.n_pad * pp->L);
+            }
             if (t_jump > 0) {
                 const int64_t cr[4] = {kx, ky, ky, kx}, cc[4] = {kx, ky, kx, ky};
                 for (int k = 0; k < 4; ++k) {
@@ -969,6 +988,41 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
     if (seg)
         for (int k = 0; k < seg->K; ++k)
             seg->S[k] = balanced ? seg_S[k] : -(rho + 0.5 * eps_blur) * seg_S[k];
+    if (pp) {
+        // kept blocks of the cross problem (rows x, columns y) at the final potentials
+        SKH_HIP(skh::launch_cluster_max(F, wX, cx.poff, kx, cmax[0], s));
+        SKH_HIP(skh::launch_cluster_max(G, wY, cy.poff, ky, cmax[1], s));
+        const double lam_b = damping(P.blur, P.reach, pc);
+        SKH_HIP(skh::launch_block_ranges(kx, ky, cmax[0], cmax[1], dist[3], cx.radius, cy.radius,
+                                         cy.poff, cy.off, cx.off, lam_b,
+                                         P.trunc_theta * eps_blur, P.trunc_theta > 0.0 ? 0 : 1,
+                                         batch.job[3].range_cap, ranges[3], rcount[3], pairs_ctr,
+                                         s));
+        SKH_HIP(skh::launch_permute_rows(pp->V, cy.perm_pad, (int)cy.n_pad, pp->L, pp_V, s));
+        skh::PlanBatch pb{};
+        pb.n_jobs = 1;
+        pb.d = d;
+        pb.kscale = (float)(kLog2e / eps_blur);
+        skh::PlanJob &PJ = pb.job[0];
+        PJ.rows = cx.Xf;
+        PJ.cols = cy.Xf;
+        PJ.u = u[3];  // offsets of g on the y columns at eps = blur^2
+        PJ.V = pp_V;
+        PJ.part = pp_part;
+        PJ.n_rows = (int)cx.n_pad;
+        PJ.n_cols = (int)cy.n_pad;
+        PJ.L = pp->L;
+        PJ.tiles = cx.tiles;
+        PJ.n_tiles = cx.n_tiles;
+        PJ.ranges = ranges[3];
+        PJ.range_count = rcount[3];
+        PJ.range_cap = batch.job[3].range_cap;
+        const int pwgs = skh::plan_plan_batch(pb, target_wgs(ctx));
+        SKH_HIP(skh::launch_plan_weighted(pb, kp, pp_lp, pwgs, s));
+        SKH_HIP(skh::launch_plan_finish(pp_part, 1, (int)cx.n_pad, pp->L, cx.hn, F, nullptr,
+                                        eps_blur, pp_out, nullptr, s));
+        SKH_HIP(skh::launch_unpermute_rows(pp_out, cx.perm_pad, (int)cx.n_pad, pp->L, pp->out, s));
+    }
     double ms_softmin = 0.0;
     if (P.timing) {
         for (int k = 0; k < launches; ++k) {
@@ -1237,9 +1291,17 @@ int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, 
         SKH_HIP(hipMemsetAsync(q, 0, sizeof(float) * m, s));
     }
     double S = 0.0;
+    SKH_HIP(skh::launch_one_hot(labels, m, L, V, s));
+    if (P.multiscale) {
+        // the plan runs inside the solve, over the cluster blocks kept at the final potentials
+        const PostPlan pp{V, L, aug};
+        const int rc = solve(ctx, X, A, na, y, b, m, d, &P, &S, f, g, p, q, stats, nullptr, &pp);
+        if (rc < 0) return rc;
+        SKH_HIP(skh::launch_label_fold(aug, n, L, flip_points ? 1 : 0, lab, score, s));
+        return rc;
+    }
     const int rc = skh_sinkhorn_divergence(ctx, X, A, na, y, b, m, d, &P, &S, f, g, p, q, stats);
     if (rc < 0) return rc;
-    SKH_HIP(skh::launch_one_hot(labels, m, L, V, s));
     const int rc2 = skh_plan_apply(ctx, X, A, na, y, b, m, d, f, g, P.blur * P.blur, V, L, 1, aug,
                                    nullptr);
     if (rc2) return rc2;

@@ -507,6 +507,43 @@ hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, flo
     return hipGetLastError();
 }
 
+// L values per point: out[p][l] = src[perm_pad[p]][l] (0 on padding), and back:
+// out[perm_pad[p]][l] = in[p][l] for real points.
+__global__ __launch_bounds__(kT) void k_permute_rows(const float *__restrict__ src,
+                                                     const int *__restrict__ perm_pad, int n_pad,
+                                                     int L, float *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= (int64_t)n_pad * L) return;
+    const int p = (int)(e / L), l = (int)(e - (int64_t)p * L);
+    const int i = perm_pad[p];
+    out[e] = i >= 0 ? src[(size_t)i * L + l] : 0.0f;
+}
+__global__ __launch_bounds__(kT) void k_unpermute_rows(const float *__restrict__ in,
+                                                       const int *__restrict__ perm_pad, int n_pad,
+                                                       int L, float *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= (int64_t)n_pad * L) return;
+    const int p = (int)(e / L), l = (int)(e - (int64_t)p * L);
+    const int i = perm_pad[p];
+    if (i >= 0) out[(size_t)i * L + l] = in[e];
+}
+
+hipError_t launch_permute_rows(const float *src, const int *perm_pad, int n_pad, int L, float *out,
+                               hipStream_t s) {
+    if (n_pad == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_rows, dim3(blocks((int64_t)n_pad * L)), dim3(kT), 0, s, src,
+                       perm_pad, n_pad, L, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_rows(const float *in, const int *perm_pad, int n_pad, int L,
+                                 float *out, hipStream_t s) {
+    if (n_pad == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute_rows, dim3(blocks((int64_t)n_pad * L)), dim3(kT), 0, s, in,
+                       perm_pad, n_pad, L, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_permute(const float *src, const int *perm_pad, int n_pad, float *out,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_permute, dim3(blocks(n_pad)), dim3(kT), 0, s, src, perm_pad, n_pad, out);

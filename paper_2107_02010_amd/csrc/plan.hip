@@ -53,14 +53,32 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
     const int n_rows = J.n_rows, n_cols = J.n_cols, L = J.L;
     const int row_tiles = J.row_tiles, chunk_cols = J.chunk_cols;
     const int local = wg - J.wg_begin;
-    const int rt = local % row_tiles, chunk = local / row_tiles;
     const int d = B.d;
     const float kscale = B.kscale;
+    int rb, re, chunk, nranges;
+    const int2 *rng = nullptr;
+    int c_begin = 0, c_end = 0;
+    if (J.tiles) {
+        const int4 t = J.tiles[local];
+        rb = t.x;
+        re = t.y;
+        chunk = 0;
+        rng = J.ranges + (size_t)t.z * J.range_cap;
+        nranges = J.range_count[t.z];
+    } else {
+        const int rt = local % row_tiles;
+        chunk = local / row_tiles;
+        rb = rt * kRowsPerBlock;
+        re = min(n_rows, rb + kRowsPerBlock);
+        c_begin = chunk * chunk_cols;
+        c_end = min(n_cols, c_begin + chunk_cols);
+        nranges = 1;
+    }
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, li = lane & 31;
-    const int i = rt * kRowsPerBlock + wave * 32 + li;
-    const int ic = i < n_rows ? i : n_rows - 1;
+    const int i = rb + wave * 32 + li;
+    const int ic = i < re ? i : re - 1;
 
     float xr[H];
     {
@@ -71,8 +89,6 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
         for (int s = 0; s < H; ++s) xr[s] = (h * H + s == d) ? 1.0f : xr[s] * kscale;
     }
 
-    const int c_begin = chunk * chunk_cols;
-    const int c_end = min(n_cols, c_begin + chunk_cols);
     float m = ninf(), wsum = 0.0f;
     float vacc[kMfmaValues ? 1 : LP];
 #pragma unroll
@@ -83,6 +99,11 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) pacc[t][r] = 0.0f;
 
+    for (int ri = 0; ri < nranges; ++ri) {
+    if (rng) {
+        c_begin = rng[ri].x;
+        c_end = rng[ri].y;
+    }
     for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
         __syncthreads();
         for (int e = tid; e < kColsPerTile * V4; e += 256) {
@@ -175,13 +196,15 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
         }
     }
 
+    }  // ranges
+
     const int RW = L + 2;
-    float *rec = part + ((size_t)chunk * n_rows + i) * RW;
+    float *rec = part + ((size_t)chunk * n_rows + ic) * RW;
     if constexpr (kMfmaValues) {
         // the level is row-uniform and each value sum is complete in one lane:
         // lane (li, h) holds values 32 t + 8 (r / 4) + 4 h + r % 4 of row li
         const float W = wsum + __shfl_xor(wsum, 32, 64);
-        if (i < n_rows) {
+        if (i < re) {
 #pragma unroll
             for (int t = 0; t < NT2; ++t)
 #pragma unroll
@@ -207,9 +230,9 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
         for (int l = 0; l < LP; ++l) {
             const float o = __shfl_xor(vacc[l], 32, 64);
             const float val = vacc[l] * s1 + o * s2;
-            if (h == 0 && i < n_rows && l < L) rec[2 + l] = val;
+            if (h == 0 && i < re && l < L) rec[2 + l] = val;
         }
-        if (h == 0 && i < n_rows) {
+        if (h == 0 && i < re) {
             rec[0] = M;
             rec[1] = W;
         }
@@ -222,6 +245,19 @@ int plan_plan_batch(PlanBatch &b, int target_wgs) {
         PlanJob &J = b.job[q];
         J.row_tiles = (J.n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
         row_tiles_total += J.row_tiles;
+    }
+    bool sparse = false;
+    for (int q = 0; q < b.n_jobs; ++q) sparse = sparse || b.job[q].tiles != nullptr;
+    if (sparse) {  // block-sparse: one workgroup per row tile, one chunk
+        int total = 0;
+        for (int q = 0; q < b.n_jobs; ++q) {
+            PlanJob &J = b.job[q];
+            J.chunk_cols = 0;
+            J.n_chunks = 1;
+            J.wg_begin = total;
+            total += J.n_tiles;
+        }
+        return total;
     }
     int want_chunks = row_tiles_total > 0 ? (target_wgs + row_tiles_total - 1) / row_tiles_total : 1;
     if (want_chunks < 1) want_chunks = 1;

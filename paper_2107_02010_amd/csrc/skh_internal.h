@@ -82,6 +82,13 @@ struct PlanJob {
     float *part;        // n_chunks x n_rows records [M, W, P_0 .. P_{L-1}]
     int n_rows, n_cols, L;
     int row_tiles, n_chunks, chunk_cols, wg_begin;
+    // Block-sparse mode (tiles != NULL), as in SoftminJob: workgroup w takes the rows
+    // tiles[w] = {begin, end, row cluster, 0} against that cluster's column ranges.
+    const int4 *tiles;
+    const int2 *ranges;
+    const int *range_count;
+    int range_cap;
+    int n_tiles;
 };
 struct PlanBatch {
     PlanJob job[kMaxJobs];
@@ -132,6 +139,10 @@ hipError_t launch_pack_padded(const float *X, const float *w, const int *perm_pa
 hipError_t launch_blk_centroids(const int *blk_cluster, const float *C, int nblk, int kp,
                                 float *blk_cent, hipStream_t s);
 hipError_t launch_unpack_centres(const float *C, int k, int d, int kp, const float *centre,
+                                 float *out, hipStream_t s);
+hipError_t launch_permute_rows(const float *src, const int *perm_pad, int n_pad, int L, float *out,
+                               hipStream_t s);
+hipError_t launch_unpermute_rows(const float *in, const int *perm_pad, int n_pad, int L,
                                  float *out, hipStream_t s);
 hipError_t launch_unpermute(const float *in, const int *perm_pad, int n_pad, float *out,
                             hipStream_t s);

@@ -73,6 +73,37 @@ def test_label_transfer_multiscale_fibres():
     assert np.all(score[inl] > 0.5)
 
 
+@pytest.mark.parametrize("theta", [20.0, 0.0])
+def test_label_transfer_multiscale_plan_matches_dense(theta):
+    # The multiscale path applies the plan over the cluster blocks kept at the final
+    # potentials (theta <= 0 keeps every block); the dense plan on the same potentials
+    # (the solve is deterministic: same inputs, same vectors) differs by the dropped
+    # blocks, whose entries are below e^{-theta} each, and by FP32 rounding.
+    import torch
+
+    import paper_2107_02010_amd as skh
+    x, a, y, b, ly, lx = _case(2500, 3100, 5, 37, 4, seed=80)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.7, multiscale=True, trunc_theta=theta,
+              n_clusters=24, tol=0.0)
+    note(f"label transfer multiscale plan vs dense theta={theta}")
+    lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 5,
+                                    flip_points=4, **kw)
+    xa = np.ascontiguousarray(np.concatenate([x, oracle.flip_fibers(x, 4)]), np.float32)
+    aa = np.ascontiguousarray(np.concatenate([a, a]), np.float32)
+    _, pot, _ = skh.sinkhorn_divergence(cuda(xa), cuda(aa), cuda(y), cuda(b), potentials=True,
+                                        **kw)
+    V = torch.nn.functional.one_hot(_labels(ly).long(), 5).float()
+    aug = host(skh.plan_apply(cuda(xa), cuda(aa), cuda(y), cuda(b), pot["f"], pot["g"], 1.0, V,
+                              divide_by_a=True))
+    n = len(x)
+    ref = aug[:n] + aug[n:]
+    rs = ref.sum(1)
+    lab, score = host(lab), host(score)
+    tol = 1e-4 * rs[:, None] + (1e-7 if theta > 0 else 1e-30)
+    assert np.all(np.abs(lab - ref) <= tol), np.abs(lab - ref).max()
+    np.testing.assert_allclose(score, rs, rtol=1e-4, atol=1e-7 if theta > 0 else 1e-30)
+
+
 def test_label_transfer_rejects_bad_arguments():
     import torch
 
