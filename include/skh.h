@@ -57,7 +57,9 @@ enum { SKH_FP32 = 0, SKH_BF16_SPLIT = 1 };
  * already known can be left out: its vectors are read from the caller's
  * buffers (whatever init says), never updated, and its problems drop out of
  * the launches and of the marginal check.  With the same scale list the other
- * vectors come out exactly as in the full solve.  Dense solves only. */
+ * vectors come out exactly as in the full solve.  SKH_FIX_CROSS needs a dense
+ * solve; SKH_FIX_P and SKH_FIX_Q also apply to multiscale solves (the coarse
+ * loop, the jump and the block masks then skip the fixed self problems too). */
 enum { SKH_FIX_P = 1, SKH_FIX_Q = 2, SKH_FIX_CROSS = 4 };
 
 /* skh_params.init: where the dual vectors start. */
@@ -282,8 +284,8 @@ int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const
  * i add up in Lab_i (the plan keeps the better-oriented one).  0: no flips.
  * params: blur, reach, scaling, tolerance, multiscale settings as for
  * skh_sinkhorn_divergence; init must be SKH_INIT_COLD, fixed 0 and labels_x/y
- * NULL (the entry runs its own solve; a dense solve holds the unused self loops
- * fixed).  labels: m ints in [0, L) (device), 1 <= L <= 64.  Outputs (device,
+ * NULL (the entry runs its own solve and holds the self loops, unused by eq. (7),
+ * fixed at zero).  labels: m ints in [0, L) (device), 1 <= L <= 64.  Outputs (device,
  * caller order, each nullable but not both): lab (n x L), score (n).  stats as
  * for skh_sinkhorn_divergence (of the augmented problem).
  * Returns SKH_OK, SKH_NOT_CONVERGED (outputs valid), or an error: SKH_EINVAL for

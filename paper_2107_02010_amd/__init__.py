@@ -128,7 +128,8 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     x (n, d), a (n,), y (m, d), b (m,): CUDA tensors.  reach=None is balanced.
     tol > 0 selects converged mode (iterate at blur until the marginal error <= tol).
     init: optional (f, g, p, q) starting potentials; the schedule then starts at start_scale
-    (<= 0: the diameter rule).  checked_init=True: non-finite starting values are discarded
+    (<= 0: the diameter rule).  Entries left None start cold (the schedule and multiscale
+    phases as without init); every vector of a fixed loop must then be given.  checked_init=True: non-finite starting values are discarded
     and the call runs cold (stats["warm_fallback"] = 1).  fixed: SKH_FIX_* bits of the loops
     whose vectors are inputs (taken from init) and stay as given.  labels: optional (labels_x,
     labels_y) int32 cluster labels that replace the K-means on the clustered paths.
@@ -162,7 +163,18 @@ def sinkhorn_divergence(x, a, y, b, blur: float = 0.05, reach=None, scaling: flo
     if fixed and init is None:
         raise ValueError("fixed dual vectors are passed through init=(f, g, p, q)")
     dev = x.device
-    if init is not None:
+    if init is not None and any(v is None for v in init):
+        # cold start for the vectors left out; the fixed ones are read as given
+        need = (fixed & _lib.SKH_FIX_CROSS, fixed & _lib.SKH_FIX_CROSS, fixed & _lib.SKH_FIX_P,
+                fixed & _lib.SKH_FIX_Q)
+        vecs = []
+        for v, k, nm, nd in zip(init, (n, m, n, m), ("f", "g", "p", "q"), need):
+            if v is None and nd:
+                raise ValueError(f"the fixed vector {nm} must be given")
+            vecs.append(torch.empty(k, dtype=torch.float32, device=dev) if v is None
+                        else _as_vec(v, k, nm, dev).clone())
+        f, g, p, q = vecs
+    elif init is not None:
         f, g, p, q = (_as_vec(v, k, nm, dev).clone() for v, k, nm in
                       zip(init, (n, m, n, m), ("f", "g", "p", "q")))
         P.init = _lib.SKH_INIT_WARM if checked_init else _lib.SKH_INIT_GIVEN

@@ -354,8 +354,8 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
     const int fixed = P.fixed;
     if (fixed & ~(SKH_FIX_P | SKH_FIX_Q | SKH_FIX_CROSS))
         return fail(ctx, SKH_EINVAL, "unknown fixed bits");
-    if (fixed && P.multiscale)
-        return fail(ctx, SKH_EINVAL, "fixed dual vectors need a dense solve");
+    if ((fixed & SKH_FIX_CROSS) && P.multiscale)
+        return fail(ctx, SKH_EINVAL, "a fixed cross loop needs a dense solve");
     if (((fixed & SKH_FIX_P) && !p) || ((fixed & SKH_FIX_Q) && !q) ||
         ((fixed & SKH_FIX_CROSS) && (!f || !g)))
         return fail(ctx, SKH_EINVAL, "fixed dual vectors must be given");
@@ -621,7 +621,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         batch.job[k].n_rows = skip_job[k] ? 0 : (int)nr[k];
         batch.job[k].n_cols = (int)nc[k];
         if (ms) {
-            batch.job[k].n_tiles = rowc[k]->n_tiles;
+            batch.job[k].n_tiles = skip_job[k] ? 0 : rowc[k]->n_tiles;
             batch.job[k].range_cap = colc[k]->k / 2 + 2;
             batch.job[k].tiles = rowc[k]->tiles;  // marks block-sparse mode for planning
         }
@@ -646,9 +646,9 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         jbatch.d = d;
         const int64_t cr[4] = {kx, ky, ky, kx}, cc[4] = {kx, ky, kx, ky};
         for (int k = 0; k < 4; ++k) {
-            cbatch.job[k].n_rows = (int)cr[k];
+            cbatch.job[k].n_rows = skip_job[k] ? 0 : (int)cr[k];
             cbatch.job[k].n_cols = (int)cc[k];
-            jbatch.job[k].n_rows = (int)nr[k];
+            jbatch.job[k].n_rows = skip_job[k] ? 0 : (int)nr[k];
             jbatch.job[k].n_cols = (int)cc[k];
         }
         cwgs = skh::plan_softmin_batch(cbatch, target_wgs(ctx));
@@ -755,7 +755,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
             cbatch.job[k].part = cpart[k];
         }
         skh::FinishSide csx{}, csy{};
-        csx.part_self = cpart[0];
+        csx.part_self = skip_job[0] ? nullptr : cpart[0];
         csx.part_cross = cpart[3];
         csx.chunks_self = cbatch.job[0].n_chunks;
         csx.chunks_cross = cbatch.job[3].n_chunks;
@@ -767,7 +767,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         csx.pot_cross = Fc;
         csx.u_self = uc[0];
         csx.u_cross = uc[2];
-        csy.part_self = cpart[1];
+        csy.part_self = skip_job[1] ? nullptr : cpart[1];
         csy.part_cross = cpart[2];
         csy.chunks_self = cbatch.job[1].n_chunks;
         csy.chunks_cross = cbatch.job[2].n_chunks;
@@ -779,7 +779,8 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         csy.pot_cross = Gc;
         csy.u_self = uc[1];
         csy.u_cross = uc[3];
-        const double cpairs = (double)kx * kx + (double)ky * ky + 2.0 * (double)kx * ky;
+        const double cpairs = (skip_job[0] ? 0.0 : (double)kx * kx) +
+                              (skip_job[1] ? 0.0 : (double)ky * ky) + 2.0 * (double)kx * ky;
         for (int it = 0; it < t_jump; ++it) {
             const double sigma = sigma_at(it), eps = powp(sigma), sn = sigma_at(it + 1);
             cbatch.kscale = (float)(kLog2e / eps);
@@ -807,9 +808,11 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         const float *jhn[4] = {hnX, hnY, hnY, hnX};
         float *jout[4] = {Pp, Q, G, F};
         for (int k = 0; k < 4; ++k)
-            SKH_HIP(skh::launch_softmin_finish(jpart[k], jbatch.job[k].n_chunks, nr[k], jhn[k], ej,
-                                               lj, jout[k], s));
-        pairs += (double)n * kx + (double)m * ky + (double)m * kx + (double)n * ky;
+            if (!skip_job[k])
+                SKH_HIP(skh::launch_softmin_finish(jpart[k], jbatch.job[k].n_chunks, nr[k], jhn[k],
+                                                   ej, lj, jout[k], s));
+        pairs += (skip_job[0] ? 0.0 : (double)n * kx) + (skip_job[1] ? 0.0 : (double)m * ky) +
+                 (double)m * kx + (double)n * ky;
     }
 
     // ---- Fine phase ----
@@ -897,14 +900,16 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
             const int keep_all = P.trunc_theta > 0.0 ? 0 : 1;
             const double te = P.trunc_theta * eps;
             // rows x / cols x (p), rows y / cols y (q), rows y / cols x (g, f), rows x / cols y (f, g)
-            SKH_HIP(skh::launch_block_ranges(kx, kx, cmax[2], cmax[2], dist[0], cx.radius, cx.radius,
-                                             cx.poff, cx.off, cx.off, lam, te, keep_all,
-                                             batch.job[0].range_cap, ranges[0], rcount[0],
-                                             pairs_ctr, s));
-            SKH_HIP(skh::launch_block_ranges(ky, ky, cmax[3], cmax[3], dist[1], cy.radius, cy.radius,
-                                             cy.poff, cy.off, cy.off, lam, te, keep_all,
-                                             batch.job[1].range_cap, ranges[1], rcount[1],
-                                             pairs_ctr, s));
+            if (!skip_job[0])
+                SKH_HIP(skh::launch_block_ranges(kx, kx, cmax[2], cmax[2], dist[0], cx.radius,
+                                                 cx.radius, cx.poff, cx.off, cx.off, lam, te,
+                                                 keep_all, batch.job[0].range_cap, ranges[0],
+                                                 rcount[0], pairs_ctr, s));
+            if (!skip_job[1])
+                SKH_HIP(skh::launch_block_ranges(ky, ky, cmax[3], cmax[3], dist[1], cy.radius,
+                                                 cy.radius, cy.poff, cy.off, cy.off, lam, te,
+                                                 keep_all, batch.job[1].range_cap, ranges[1],
+                                                 rcount[1], pairs_ctr, s));
             SKH_HIP(skh::launch_block_ranges(ky, kx, cmax[1], cmax[0], dist[2], cy.radius, cx.radius,
                                              cx.poff, cx.off, cy.off, lam, te, keep_all,
                                              batch.job[2].range_cap, ranges[2], rcount[2],
@@ -1280,15 +1285,16 @@ int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, 
         return fail(ctx, SKH_EINVAL, "atlas label out of range [0, L)");
     if (flip_points) SKH_HIP(skh::launch_flip_augment(x, a, n, d, flip_points, xa, aa, s));
     const float *X = flip_points ? xa : x, *A = flip_points ? aa : a;
-    // only the cross loop is needed: the dense solve holds the self loops fixed at zero
+    // only the cross loop is needed (eq. (7) uses f and g alone): the self loops stay
+    // fixed at zero
     skh_params P = *params;
-    if (!P.multiscale) {
-        P.fixed = SKH_FIX_P | SKH_FIX_Q;
+    P.fixed = SKH_FIX_P | SKH_FIX_Q;
+    SKH_HIP(hipMemsetAsync(p, 0, sizeof(float) * na, s));
+    SKH_HIP(hipMemsetAsync(q, 0, sizeof(float) * m, s));
+    if (!P.multiscale) {  // dense: the cross loop starts from given zeros
         P.init = SKH_INIT_GIVEN;
         SKH_HIP(hipMemsetAsync(f, 0, sizeof(float) * na, s));
-        SKH_HIP(hipMemsetAsync(p, 0, sizeof(float) * na, s));
         SKH_HIP(hipMemsetAsync(g, 0, sizeof(float) * m, s));
-        SKH_HIP(hipMemsetAsync(q, 0, sizeof(float) * m, s));
     }
     double S = 0.0;
     SKH_HIP(skh::launch_one_hot(labels, m, L, V, s));

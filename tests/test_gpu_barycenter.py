@@ -98,7 +98,7 @@ def test_fixed_loops_argument_checks():
     with pytest.raises(skh.SkhError):
         skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=8)
     with pytest.raises(skh.SkhError):
-        skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=skh.SKH_FIX_P,
+        skh.sinkhorn_divergence(X, A, Y, B, init=(z, z, z, z), fixed=skh.SKH_FIX_CROSS,
                                 multiscale=True)
 
 

@@ -79,3 +79,37 @@ def test_multiscale_blob_config_balanced():
     S, pot, st = _run(x, a, y, b, multiscale=True, jump_scale=-1.0, trunc_theta=20.0, **kw)
     Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 0.01, None, scaling=0.5)
     assert S == pytest.approx(Sr, rel=1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_multiscale_fixed_self_loops_keep_the_cross_vectors(precision):
+    # The self loops are independent of the cross loop (coarse loop, jump, masks and
+    # fine loop alike): holding p, q fixed at any given values leaves f, g as in the
+    # full multiscale solve with the same scale list, and drops the self problems'
+    # pairs.
+    import torch
+
+    import paper_2107_02010_amd as skh
+    x, a, y, b = synth.fiber_pair(5000, 25, seed=24)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.8, extra_iters=3, multiscale=True,
+              precision=precision, n_clusters=40)
+    note(f"multiscale fixed self loops {precision}")
+    S0, pot0, st0 = skh.sinkhorn_divergence(X, A, Y, B, potentials=True, **kw)
+    zp, zq = torch.zeros(len(x), device="cuda"), torch.zeros(len(y), device="cuda")
+    S1, pot1, st1 = skh.sinkhorn_divergence(X, A, Y, B, potentials=True,
+                                            init=(None, None, zp, zq),
+                                            fixed=skh.SKH_FIX_P | skh.SKH_FIX_Q, **kw)
+    assert st1["iters"] == st0["iters"] and st1["coarse_iters"] == st0["coarse_iters"]
+    assert st1["coarse_iters"] > 0
+    assert st1["pairs"] < 0.75 * st0["pairs"]
+    scale = max(1.0, float(torch.abs(pot0["f"]).max()))
+    for k in ("f", "g"):
+        assert torch.max(torch.abs(pot1[k] - pot0[k])).item() <= 1e-6 * scale
+    assert torch.equal(pot1["p"], zp) and torch.equal(pot1["q"], zq)
+    with pytest.raises(ValueError):  # a fixed vector left out
+        skh.sinkhorn_divergence(X, A, Y, B, init=(None, None, None, zq),
+                                fixed=skh.SKH_FIX_P | skh.SKH_FIX_Q, **kw)
+    with pytest.raises(skh.SkhError):  # the cross loop cannot be fixed on this path
+        skh.sinkhorn_divergence(X, A, Y, B, init=(pot0["f"], pot0["g"], None, None),
+                                fixed=skh.SKH_FIX_CROSS, **kw)
