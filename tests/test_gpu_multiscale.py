@@ -113,3 +113,62 @@ def test_multiscale_fixed_self_loops_keep_the_cross_vectors(precision):
     with pytest.raises(skh.SkhError):  # the cross loop cannot be fixed on this path
         skh.sinkhorn_divergence(X, A, Y, B, init=(pot0["f"], pot0["g"], None, None),
                                 fixed=skh.SKH_FIX_CROSS, **kw)
+
+
+def _fixed_point_deviation(rows_pts, cols_pts, cols_w, pot_rows, pot_cols, eps, rho):
+    """Relative deviation of sampled rows from the unbalanced fixed point, with the FP64
+    oracle's dense softmin over every column: the row mass of the plan over its target,
+    r_i / (w_i e^{-f_i / rho}) - 1 = expm1((f_i - f~_i) / eps + f_i / rho), where
+    f~_i = -eps log sum_j w_j exp((g_j - C_ij) / eps) (eq. (4) and the Algorithm's update
+    with lambda = rho / (rho + eps): at the fixed point f = lambda f~)."""
+    ft = oracle.softmin(rows_pts, cols_pts, cols_w, pot_cols, eps, 1.0)
+    return np.abs(np.expm1((pot_rows - ft) / eps + pot_rows / rho))
+
+
+def test_multiscale_1m_fibres_full_size():
+    # The 1M x 1M fibre workload of the benchmark (200 bundles, blur 1 mm, reach 20 mm,
+    # K-means sqrt(n) clusters, truncation theta 20, marginal tolerance 1e-4) in the two
+    # configurations it times: plain FP32 multiscale and BF16 split + learned warm start.
+    # S agrees within 1e-3; sampled rows and columns of every dual vector sit at the
+    # fixed point of the dense problem, checked by the FP64 oracle against all 1M points
+    # (no clustering, no truncation).
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd.warm_start import (DEFAULT_CHECKPOINT, WarmStartNet,
+                                                 sinkhorn_divergence_warm)
+    n = 1_000_000
+    note("multiscale 1M fibres: generating the clouds")
+    x, a, y, b = synth.fiber_pair(n, 200, seed=0)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    kw = dict(reach=20.0, tol=1e-4, check_every=5, max_iters=20000, multiscale=True)
+    note("multiscale 1M fibres: plain FP32 solve")
+    S0, pot0, st0 = skh.sinkhorn_divergence(X, A, Y, B, blur=1.0, scaling=0.9, potentials=True,
+                                            precision="fp32", **kw)
+    note("multiscale 1M fibres: BF16 split + warm start")
+    net = WarmStartNet.load(DEFAULT_CHECKPOINT, "cuda:0")
+    S1, pot1, st1 = sinkhorn_divergence_warm(net, X, A, Y, B, 1.0, scaling=0.9,
+                                             precision="bf16x3", **kw)
+    assert st0["converged"] and st1["converged"] and st1["warm_fallback"] == 0
+    assert st0["pairs"] < 0.2 * st0["dense_pairs"]
+    print(f"S fp32 {S0:.9g} bf16+warm {S1:.9g} rel {abs(S1 - S0) / abs(S0):.2e}")
+    assert abs(S1 - S0) <= 1e-3 * abs(S0)
+    rng = np.random.default_rng(17)
+    ri = np.sort(rng.choice(n, size=40, replace=False))
+    ri[-1] = n - 1
+    eps, rho = 1.0, 400.0
+    # The stopping rule bounds the relative L1 marginal error by 1e-4 (measured by the
+    # solver in its own precision): a sample's mean deviation stays within a few times
+    # that, single rows within 50 times; the BF16 split adds its contraction error
+    # (about 1e-4 of eps in f~ on clustered fibres).
+    for tag, pot, mean_bound, max_bound in (("fp32", pot0, 5e-4, 5e-3),
+                                            ("bf16x3+warm", pot1, 1e-3, 1e-2)):
+        P = {k: host(v).astype(np.float64) for k, v in pot.items()}
+        devs = [
+            _fixed_point_deviation(x[ri], y, b, P["f"][ri], P["g"], eps, rho),  # f vs g
+            _fixed_point_deviation(y[ri], x, a, P["g"][ri], P["f"], eps, rho),  # g vs f
+            _fixed_point_deviation(x[ri], x, a, P["p"][ri], P["p"], eps, rho),  # p vs p
+            _fixed_point_deviation(y[ri], y, b, P["q"][ri], P["q"], eps, rho),  # q vs q
+        ]
+        for name, dv in zip("fgpq", devs):
+            print(f"{tag} {name}: mean deviation {dv.mean():.2e}, max {dv.max():.2e}")
+            assert np.all(np.isfinite(dv))
+            assert dv.mean() <= mean_bound and dv.max() <= max_bound, (tag, name)
