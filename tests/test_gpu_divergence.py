@@ -71,6 +71,28 @@ def test_fiber_downscaled_unbalanced_fp32():
     _compare(x, a, y, b, blur=1.0, reach=20.0, scaling=0.8, extra=3)
 
 
+def test_fiber_200k_full_size_bf16_against_fp32():
+    # The benchmark's default step at full size (200k x 200k 60-D fibres, 50 bundles,
+    # blur 1 mm, balanced, scaling 0.9, dense): the BF16 split solve it times against
+    # the FP32 solve (pinned to the oracle at small sizes) on the same schedule.
+    import paper_2107_02010_amd as skh
+    x, a, y, b = synth.fiber_pair(200_000, 50, seed=0)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    kw = dict(blur=1.0, reach=None, scaling=0.9, potentials=True)
+    note("fibres 200k full size: FP32 solve")
+    S0, pot0, st0 = skh.sinkhorn_divergence(X, A, Y, B, precision="fp32", **kw)
+    note("fibres 200k full size: BF16 split solve")
+    S1, pot1, st1 = skh.sinkhorn_divergence(X, A, Y, B, precision="bf16x3", **kw)
+    assert st0["iters"] == st1["iters"] > 40
+    print(f"S fp32 {S0:.9g} bf16 {S1:.9g} rel {abs(S1 - S0) / abs(S0):.2e}")
+    assert abs(S1 - S0) <= 1e-3 * abs(S0)
+    scale = max(1.0, float(pot0["f"].abs().max()))
+    for k in ("f", "g", "p", "q"):
+        dg = host(pot1[k]).astype(np.float64) - host(pot0[k]).astype(np.float64)
+        dg -= dg.mean()  # balanced: potentials are defined up to a constant
+        assert np.max(np.abs(dg)) <= 1e-3 * scale, (k, np.max(np.abs(dg)))
+
+
 @pytest.mark.parametrize("n,m,d", [(1, 1, 3), (1, 37, 2), (130, 1, 5), (257, 129, 1), (5, 300, 60)])
 def test_edge_sizes(n, m, d):
     rng = np.random.default_rng(n + m + d)

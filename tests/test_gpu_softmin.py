@@ -95,6 +95,33 @@ def test_softmin_fiber_full_size_sampled_rows():
 
 # ------------------------------------------------------------- BF16 split ---
 
+def test_softmin_bf16_fiber_full_size_sampled_rows():
+    # the benchmark's 200k x 200k fibre shape on the BF16 split path (its chosen
+    # precision): sampled rows against all 200k columns in FP64, within the FP32 bound
+    # plus the split bound of _check_bf16 (any cluster centre lies in the cloud's hull)
+    import paper_2107_02010_amd as skh
+    from gpu_common import centred
+    x, a, y, b = synth.fiber_pair(200_000, 50, seed=12)
+    rng = np.random.default_rng(8)
+    h = (2.0 * rng.standard_normal(200_000)).astype(np.float32)
+    rows = np.sort(rng.choice(200_000, size=64, replace=False))
+    rows[-1] = 199_999
+    xc, yc = centred(x, y)
+    for eps in (1.0, 400.0):
+        note(f"softmin bf16 fibres 200k eps={eps}")
+        out = host(skh.softmin(cuda(x), cuda(y), cuda(b), cuda(h), eps, 1.0,
+                               precision="bf16x3"))
+        ref = oracle.softmin(x[rows], y, b, h, eps, 1.0)
+        bound = softmin_fp32_bound(np.concatenate([x[rows], x]), y, b.astype(np.float64),
+                                   h.astype(np.float64), eps, 1.0,
+                                   np.concatenate([ref, np.zeros(len(x))]))[:len(rows)]
+        bound += 8 * 3 * 2.0 ** -16 * np.linalg.norm(xc[rows], axis=1) * 2 * \
+            np.linalg.norm(yc, axis=1).max()
+        err = np.abs(out[rows] - ref)
+        assert np.all(np.isfinite(out))
+        assert np.all(err <= bound), (eps, np.max(err / bound))
+
+
 def _check_bf16(x, y, w, h, eps, lam, tag):
     """BF16 hi/lo split: the contraction error of one pair is at most
     3 * 2^-16 |x_i| |y_j - c_J| (dropped lo.lo product and the two split residuals),
