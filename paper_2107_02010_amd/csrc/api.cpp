@@ -994,12 +994,14 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         for (int k = 0; k < seg->K; ++k)
             seg->S[k] = balanced ? seg_S[k] : -(rho + 0.5 * eps_blur) * seg_S[k];
     if (pp) {
-        // kept blocks of the cross problem (rows x, columns y) at the final potentials
+        // kept blocks of the cross problem (rows x, columns y) at the final potentials:
+        // every entry of pi / (alpha beta) in a dropped block is below e^{-theta}, since
+        // f_i + g_j - C_ij <= max_I f + max_J g - gap^2 / 2 (damping 1: the plan of
+        // eq. (4) carries f and g undamped)
         SKH_HIP(skh::launch_cluster_max(F, wX, cx.poff, kx, cmax[0], s));
         SKH_HIP(skh::launch_cluster_max(G, wY, cy.poff, ky, cmax[1], s));
-        const double lam_b = damping(P.blur, P.reach, pc);
         SKH_HIP(skh::launch_block_ranges(kx, ky, cmax[0], cmax[1], dist[3], cx.radius, cy.radius,
-                                         cy.poff, cy.off, cx.off, lam_b,
+                                         cy.poff, cy.off, cx.off, 1.0,
                                          P.trunc_theta * eps_blur, P.trunc_theta > 0.0 ? 0 : 1,
                                          batch.job[3].range_cap, ranges[3], rcount[3], pairs_ctr,
                                          s));
