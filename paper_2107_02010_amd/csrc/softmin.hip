@@ -21,9 +21,22 @@
 // column sweep).  The column offset u_j rides along as one more coordinate:
 // row slot d holds 1.0, column slot d holds u_j, so the MFMA result is s_ij
 // itself.  Output lanes index rows (i = lane % 32) and the 16 accumulator
-// registers index columns, so each lane folds its 16 values into its own
-// running (max, sum) with no cross-lane traffic; the two lane halves that
-// share a row are merged once at the end.
+// registers index columns, so each lane sums its 16 values with no cross-lane
+// traffic.
+//
+// Wide points (KP >= 16): the products dominate, and each lane keeps a running
+// (max, sum) per block; the two lane halves of a row merge once at the end.
+// Narrow points (KP <= 8, e.g. 3-D clouds): the exponentials and sums dominate,
+// so the per-block maximum is dropped.  The sum is kept relative to a reference
+// level R_i shared by the two lane halves of row i, and -R_i enters the
+// contraction as the accumulator input of the first product: the MFMA delivers
+// s_ij - R_i, one exponential and one add per pair.  R_i moves, for the rows
+// that need it, only when a row's sum would leave [2^-4, 2^59) (first mass,
+// overflow): the new level is the larger of the block's maximum and the sum so
+// far, and the block is re-summed from the accumulators.  Once every row of a
+// wave holds mass, a block whose terms all lie below 2^-48 of the level is
+// skipped after its products (with the row sum >= 2^-4 of the level, a million
+// such blocks move it by less than FP32 rounding).
 //
 // Zero weights and the ragged column tail both enter as u_j = -inf, which the
 // contraction turns into s_ij = -inf and the exponential into 0.
@@ -38,6 +51,19 @@ static __device__ __forceinline__ float ninf() { return -__builtin_huge_valf(); 
 static __device__ __forceinline__ float fast_exp2(float x) {
     return __builtin_amdgcn_exp2f(x);  // v_exp_f32; inputs below -126 flush toward 0
 }
+// sum / maximum of a value over the two lane halves that hold the same row
+static __device__ __forceinline__ float row_sum(float v) {
+    const unsigned w = __float_as_uint(v);
+    const auto t = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+static __device__ __forceinline__ float row_max(float v) {
+    const unsigned w = __float_as_uint(v);
+    const auto t = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+    return fmaxf(__uint_as_float(t[0]), __uint_as_float(t[1]));
+}
+// log2 of the largest term a skipped block may hold (relative to the level)
+constexpr float kNegligibleF32 = -48.0f;
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
@@ -110,7 +136,15 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         for (int s = 0; s < H; ++s) xr[s] = (h * H + s == d) ? 1.0f : xr[s] * kscale;
     }
 
+    constexpr bool kLevel = KP <= 8;  // reference-level form for narrow points
+    // online maximum form: running (max, sum) per lane
     float m = ninf(), acc_sum = 0.0f;
+    // reference-level form: level R (row-uniform) and this lane's sum relative to it
+    float R = 0.0f, Sl = 0.0f;
+    bool mass = false, all_mass = false;
+    v16f base;  // -R in every register: the accumulator input of the first product
+#pragma unroll
+    for (int r = 0; r < 16; ++r) base[r] = kLevel ? -R : 0.0f;
 
     for (int ri = 0; ri < nranges; ++ri) {
     if (rng) {
@@ -139,34 +173,85 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         const int nvalid = c_end - j0;
         const int nblk = wave_active ? min(kColsPerTile / 32, (nvalid + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
-            v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                        0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             const float *tp = &tile[(jb * 32 + li) * STRIDE + h * H];
+            v16f acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[0], xr[0], base, 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < H; ++s)
+            for (int s = 1; s < H; ++s)
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[s], xr[s], acc, 0, 0, 0);
-            float tmax = acc[0];
+            if constexpr (!kLevel) {  // acc[r] = s_ij
+                float tmax = acc[0];
 #pragma unroll
-            for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
-            const float mn = fmaxf(m, tmax);
-            if (mn > ninf()) {
-                float sblk = 0.0f;
+                for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
+                const float mn = fmaxf(m, tmax);
+                if (mn > ninf()) {
+                    float sblk = 0.0f;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) sblk += fast_exp2(acc[r] - mn);
-                acc_sum = acc_sum * fast_exp2(m - mn) + sblk;
-                m = mn;
+                    for (int r = 0; r < 16; ++r) sblk += fast_exp2(acc[r] - mn);
+                    acc_sum = acc_sum * fast_exp2(m - mn) + sblk;
+                    m = mn;
+                }
+                continue;
             }
+            // acc[r] = s_ij - R
+            if (all_mass) {  // wave-uniform skip of a negligible block
+                float mx = acc[0];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+                if (!__any(mx > kNegligibleF32)) continue;
+            }
+            float ex[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) ex[r] = fast_exp2(acc[r]);
+#pragma unroll
+            for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+                for (int r = 0; r < w; ++r) ex[r] += ex[r + w];
+            float Sn = Sl + ex[0];
+            if (__any(!(Sn < 0x1p59f) || !mass)) {  // wave-uniform: look at whole rows
+                const float Sc = row_sum(Sn);
+                const bool need = !(Sc < 0x1p59f) || !(Sc >= 0x1p-4f);
+                if (__any(need)) {  // wave-uniform: re-level the rows that need it
+                    float tmax = acc[0];
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) tmax = fmaxf(tmax, acc[r]);
+                    tmax = row_max(tmax);
+                    const float So = row_sum(Sl);
+                    const float lg = So > 0.0f ? __log2f(So) : ninf();
+                    const float top = fmaxf(tmax, lg);  // new level relative to R
+                    if (need && top > ninf()) {
+                        const float Rn = R + top;
+                        const float dl = R - Rn;
+                        float sb = 0.0f;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) sb += fast_exp2(acc[r] + dl);
+                        Sn = (Sl > 0.0f ? Sl * fast_exp2(dl) : 0.0f) + sb;
+                        R = Rn;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) base[r] = -R;
+                    }
+                }
+                mass = row_sum(Sn) >= 0x1p-4f;
+                all_mass = !__any(!mass);
+            }
+            Sl = Sn;
         }
     }
     }
 
-    // Merge the two lane halves that hold the same row.
-    const float m2 = __shfl_xor(m, 32, 64);
-    const float s2 = __shfl_xor(acc_sum, 32, 64);
-    const float M = fmaxf(m, m2);
-    float S = 0.0f;
-    if (M > ninf()) S = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
-    if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, S);
+    if constexpr (kLevel) {
+        // both lane halves of a row share R: the row's partial is (R, sum of both halves)
+        const float Sr = row_sum(Sl);
+        const float M = Sr > 0.0f ? R : ninf();
+        if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, Sr);
+    } else {
+        // merge the two lane halves that hold the same row
+        const float m2 = __shfl_xor(m, 32, 64);
+        const float s2 = __shfl_xor(acc_sum, 32, 64);
+        const float M = fmaxf(m, m2);
+        float S = 0.0f;
+        if (M > ninf()) S = acc_sum * fast_exp2(m - M) + s2 * fast_exp2(m2 - M);
+        if (h == 0 && i < re) part[(size_t)chunk * n_rows + i] = make_float2(M, S);
+    }
 }
 
 int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
