@@ -336,13 +336,13 @@ def bench_barycenter(args, skh, synth):
     ym = [(torch.as_tensor(c).cuda(), torch.as_tensor(w).cuda()) for c, w in maps]
     X, A = torch.as_tensor(x0).cuda(), torch.as_tensor(a).cuda()
     res = {}
-    for batched in (True, False):
-        B = Barycenter(A, ym, blur=1.0, scaling=0.9, x0=X, batched=batched)
+    for leg, batched, ms in (("batched", True, False), ("per_map", False, False),
+                             ("per_map_multiscale", False, True)):
+        B = Barycenter(A, ym, blur=1.0, scaling=0.9, x0=X, batched=batched, multiscale=ms)
         B._setup(X)  # the maps' self vectors: once for the whole descent, outside the step
         dt, (x1, S, _) = _timed(lambda: B.step(X), args.steps, args.warmup)
-        res["batched" if batched else "per_map"] = {"s_per_step": round(dt, 4), "mean_S": S}
-        print(f"[bench] barycenter step ({'batched' if batched else 'per map'}): {dt:.3f} s",
-              file=sys.stderr, flush=True)
+        res[leg] = {"s_per_step": round(dt, 4), "mean_S": S}
+        print(f"[bench] barycenter step ({leg}): {dt:.3f} s", file=sys.stderr, flush=True)
     m_total = sum(len(c) for c, _ in maps)
     out = {"metric": "time per barycenter step, 10 density maps (128^3), 200k support points",
            "value": res["batched"]["s_per_step"], "unit": "s", "n_gpus": 1,
@@ -355,7 +355,10 @@ def bench_barycenter(args, skh, synth):
                                   "scaling 0.9; self loop of the support per step, cross loops "
                                   "of all maps, 10 gradients"},
            "batched": res["batched"], "per_map": res["per_map"],
-           "speedup_batched": round(res["per_map"]["s_per_step"] / res["batched"]["s_per_step"], 3)}
+           "per_map_multiscale": res["per_map_multiscale"],
+           "speedup_batched": round(res["per_map"]["s_per_step"] / res["batched"]["s_per_step"], 3),
+           "S_rel_diff_multiscale": abs(res["per_map_multiscale"]["mean_S"] - res["batched"]["mean_S"])
+                                    / abs(res["batched"]["mean_S"])}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -18,7 +18,9 @@ common largest scale is the largest joint bounding-box diagonal over the maps
 at the start (any upper bound of the distances is a valid first scale).  In
 FP32 the K cross loops run as one batched solve: every iteration is one launch
 over all maps (row tiles of each map's copy of the support against that map's
-columns only).
+columns only).  With multiscale=True each map's cross loop runs the coarse-to-fine
+scheme of Section 2 instead (K-means coarse loop, jump, cluster-block truncation at
+e^{-trunc_theta}), from a cold start with p and q_k fixed; the self vectors stay dense.
 """
 from __future__ import annotations
 
@@ -33,12 +35,16 @@ class Barycenter:
 
     def __init__(self, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
                  lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0, x0=None,
-                 batched: bool = True):
+                 batched: bool = True, multiscale: bool = False, trunc_theta: float = 20.0,
+                 n_clusters: int = 0, tol: float = 0.0, max_iters: int = 1000):
         self.a = a
         self.maps = maps
-        self.batched = batched and precision == "fp32"
+        self.multiscale = multiscale
+        self.batched = batched and precision == "fp32" and not multiscale
+        # tol > 0: every loop iterates at blur until its marginal error is <= tol
         self.kw = dict(blur=blur, reach=reach, scaling=scaling, precision=precision,
-                       extra_iters=extra_iters)
+                       extra_iters=extra_iters, tol=tol, max_iters=max_iters)
+        self.ms_kw = dict(multiscale=True, trunc_theta=trunc_theta, n_clusters=n_clusters)
         self.lr = lr
         self.d = None if x0 is None else max(diameter(x0, y) for y, _ in maps)
         self.q = None
@@ -73,11 +79,18 @@ class Barycenter:
             grad /= K
             return x - self.lr * grad / self.a[:, None], sum(S) / K, pots
         for (y, b), q in zip(self.maps, self.q):
-            zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
-            zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
-            S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d, init=(zf, zg, p, q),
-                                            fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
-                                            **self.kw)
+            if self.multiscale:  # cold cross loop (coarse phase first), p and q fixed
+                S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d,
+                                                init=(None, None, p, q),
+                                                fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
+                                                **self.kw, **self.ms_kw)
+            else:
+                zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
+                zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
+                S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d,
+                                                init=(zf, zg, p, q),
+                                                fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
+                                                **self.kw)
             grad += grad_x(x, self.a, y, b, pot["f"], pot["g"], pot["p"], self.kw["blur"])
             total += S
             pots.append(pot)
@@ -87,12 +100,16 @@ class Barycenter:
 
 def barycenter_step(x, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
                     lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0,
-                    diameter_=None, batched: bool = True):
+                    diameter_=None, batched: bool = True, multiscale: bool = False,
+                    trunc_theta: float = 20.0, n_clusters: int = 0, tol: float = 0.0,
+                    max_iters: int = 1000):
     """One gradient step with the scale list from diameter_ (None: the largest joint
     bounding-box diagonal of x with each map).  maps: list of (y_k, b_k) CUDA tensors.
 
     Returns (new x, mean S, list of per-map potentials dicts)."""
-    B = Barycenter(a, maps, blur, reach, scaling, lr, precision, extra_iters, batched=batched)
+    B = Barycenter(a, maps, blur, reach, scaling, lr, precision, extra_iters, batched=batched,
+                   multiscale=multiscale, trunc_theta=trunc_theta, n_clusters=n_clusters,
+                   tol=tol, max_iters=max_iters)
     B.d = diameter_
     return B.step(x)
 

@@ -51,6 +51,25 @@ def test_barycenter_full_shape_one_step():
     np.testing.assert_allclose(g.astype(np.float64).mean(0), ybar, atol=0.5)
 
 
+def test_multiscale_step_matches_dense_step():
+    # each map's cross loop on the coarse-to-fine scheme (cold start, p and q fixed)
+    # against the dense cross loops, both iterated at blur to a marginal error of 1e-5:
+    # the two paths reach the same fixed point, so S and the step agree up to the
+    # tolerance and the truncation (entries below e^-20)
+    from paper_2107_02010_amd.barycenter import barycenter_step
+    maps = synth.density_maps(2, seed=7, grid=48, n_tubes=3, nonzero=(4000, 6000),
+                              sigma=(1.5, 2.5), jitter=2.0)
+    x0, a = synth.barycenter_support(maps, 3000, seed=8)
+    ym = [(cuda(c), cuda(w)) for c, w in maps]
+    kw = dict(blur=1.0, scaling=0.8, tol=1e-5, max_iters=20000)
+    note("barycenter multiscale vs dense, 2 maps 48^3, 3000 support")
+    x1, S1, p1 = barycenter_step(cuda(x0), cuda(a), ym, batched=False, **kw)
+    x2, S2, p2 = barycenter_step(cuda(x0), cuda(a), ym, multiscale=True, n_clusters=20, **kw)
+    print(f"S dense {S1:.9g} multiscale {S2:.9g}")
+    assert S2 == pytest.approx(S1, rel=1e-4)
+    np.testing.assert_allclose(host(x2), host(x1), atol=1e-2)
+
+
 def _pair(n, m, seed):
     x, a, y, b = synth.blob_pair(n, seed=seed)
     b = synth.random_weights(m, seed + 5, total=1.0) if m == n else b

@@ -121,3 +121,38 @@ def test_label_transfer_rejects_bad_arguments():
                            torch.as_tensor(ly, dtype=torch.int64).cuda(), 3)
     lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 3)
     assert torch.isfinite(lab).all() and torch.isfinite(score).all()
+
+
+@pytest.mark.parametrize("n,m,L,flips", [(1, 50, 1, 0), (3, 40, 2, 4), (130, 70, 64, 4)])
+def test_label_transfer_multiscale_edge_sizes(n, m, L, flips):
+    # tiny subjects, more clusters requested than points, one label and the largest
+    # label count: the block-sparse plan inside the multiscale solve against the dense
+    # plan on the same potentials
+    import torch
+
+    import paper_2107_02010_amd as skh
+    rng = np.random.default_rng(n + m + L)
+    x = (5.0 * rng.standard_normal((n, 12))).astype(np.float32)
+    y = (5.0 * rng.standard_normal((m, 12))).astype(np.float32)
+    a, b = synth.uniform_weights(n), synth.uniform_weights(m)
+    ly = rng.integers(0, L, m).astype(np.int32)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.7, multiscale=True, n_clusters=200, tol=0.0)
+    note(f"label transfer multiscale edge n={n} m={m} L={L} flips={flips}")
+    lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), L,
+                                    flip_points=flips, **kw)
+    if flips:
+        xa = np.ascontiguousarray(np.concatenate([x, oracle.flip_fibers(x, flips)]), np.float32)
+        aa = np.ascontiguousarray(np.concatenate([a, a]), np.float32)
+    else:
+        xa, aa = x, a
+    _, pot, _ = skh.sinkhorn_divergence(cuda(xa), cuda(aa), cuda(y), cuda(b), potentials=True,
+                                        **kw)
+    V = torch.nn.functional.one_hot(_labels(ly).long(), L).float()
+    aug = host(skh.plan_apply(cuda(xa), cuda(aa), cuda(y), cuda(b), pot["f"], pot["g"], 1.0, V,
+                              divide_by_a=True))
+    ref = aug[:n] + aug[n:] if flips else aug
+    rs = ref.sum(1)
+    lab, score = host(lab), host(score)
+    assert lab.shape == (n, L) and score.shape == (n,)
+    assert np.all(np.abs(lab - ref) <= 1e-4 * rs[:, None] + 1e-7)
+    np.testing.assert_allclose(score, rs, rtol=1e-4, atol=1e-7)
