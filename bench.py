@@ -13,8 +13,8 @@ input is timed beside it.  Inputs are resident in HBM before the timed region.
 
 --workload multiscale1m: time-to-S_eps on n = m = 1,000,000 fibres (200
 bundles), reach 20 mm, blur 1 mm, K-means coarse phase with sqrt(n) clusters,
-cluster-block truncation, converged mode (marginal error <= 1e-4 checked every
-5 iterations); plain FP32 (cold) against the BF16 split (cold) and the chosen
+cluster-block truncation, converged mode (marginal error <= 1e-4 checked after
+every iteration, --check-every); plain FP32 (cold) against the BF16 split (cold) and the chosen
 path, BF16 split + learned warm start (network trained by ws_train, loaded from
 paper_2107_02010_amd/data/ws_fibers.safetensors; tokens, network forward and the
 broadcast are inside the timed region).
@@ -376,7 +376,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-every", type=int, default=5,
+    ap.add_argument("--check-every", type=int, default=1,
                     help="multiscale1m: iterations between marginal-error checks at blur")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times), "
