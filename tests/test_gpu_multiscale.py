@@ -73,6 +73,26 @@ def test_full_multiscale_converges_to_dense_fixed_point(precision):
     assert np.abs(pot["g"] - potd["g"]).max() <= 4 * rho * tol
 
 
+def test_multiscale_200k_fibres_matches_dense_fp32():
+    # The same comparison at the 200k-fibre shape of the benchmark (50 bundles, reach
+    # 20 mm, marginal tolerance 1e-4): one dense FP32 solve against the multiscale
+    # solves in FP32 and BF16 split.
+    x, a, y, b = synth.fiber_pair(200_000, 50, seed=25)
+    kw = dict(blur=1.0, reach=20.0, scaling=0.9, tol=1e-4, max_iters=20000, check_every=1)
+    Sd, potd, std = _run(x, a, y, b, **kw)
+    assert std["converged"] == 1
+    rho, tol = 20.0 ** 2, 1e-4
+    for precision, rtol in (("fp32", 1e-5), ("bf16x3", 1e-3)):
+        S, pot, st = _run(x, a, y, b, multiscale=True, precision=precision, **kw)
+        print(f"200k multiscale {precision}: kept {st['pairs'] / max(st['dense_pairs'], 1):.4f}, "
+              f"S={S:.9g} dense={Sd:.9g} ({st['iters']} / {std['iters']} iterations)")
+        assert st["converged"] == 1 and st["coarse_iters"] > 0
+        assert st["pairs"] < 0.1 * st["dense_pairs"]
+        assert S == pytest.approx(Sd, rel=rtol)
+        assert np.abs(pot["f"] - potd["f"]).max() <= 4 * rho * tol
+        assert np.abs(pot["g"] - potd["g"]).max() <= 4 * rho * tol
+
+
 def test_multiscale_blob_config_balanced():
     x, a, y, b = synth.blob_pair(2000, seed=0)
     kw = dict(blur=0.01, reach=None, scaling=0.5)
