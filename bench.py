@@ -23,6 +23,8 @@ broadcast are inside the timed region).
 200k x 200k fibre solve (reach 20 mm); Gpair/s of the plan-weighted kernels.
 --workload labels200k: label transfer from a 200k-fibre labelled atlas to a 200k-fibre
 subject (random fibre directions, 1 % aberrant fibres) with flip augmentation.
+--workload labels250k: the same at the size of the paper's hemisphere experiment
+(250k-fibre subject, 200k-fibre atlas, blur 2 mm).
 --workload pcost200k: full solve with the cost |x - y| (p = 1) on 200k x 200k 3-D clouds.
 --workload barycenter10: one barycenter descent step over 10 density maps, 200k support.
 
@@ -245,35 +247,40 @@ def bench_gradients(args, skh, synth):
 def bench_labels(args, skh, synth):
     """Label transfer (eq. (7)) from a 200k-fibre atlas of 50 labelled bundles to a 200k-fibre
     subject stored in random directions plus 1 % aberrant fibres, with flip augmentation,
-    multiscale BF16 solve over the Algorithm's schedule."""
+    multiscale BF16 solve over the Algorithm's schedule.  labels250k: the size of the
+    paper's hemisphere experiment (250k-fibre subject, 200k-fibre atlas, blur 2 mm)."""
     import numpy as np
     import torch
-    n = args.n
+    paper_size = args.workload == "labels250k"
+    n = 250_000 if paper_size else args.n        # subject fibres
+    n_at = 200_000 if paper_size else args.n     # atlas fibres
+    blur = 2.0 if paper_size else 1.0
     nout = n // 100
-    print(f"[bench] generating atlas and subject ({n} fibres, {nout} outliers)", file=sys.stderr,
-          flush=True)
-    y = synth.fibers(n, args.bundles, spine_seed=0, seed=1)
-    ly = synth.fiber_labels(n, args.bundles)
+    print(f"[bench] generating atlas ({n_at} fibres) and subject ({n} fibres, {nout} outliers)",
+          file=sys.stderr, flush=True)
+    y = synth.fibers(n_at, args.bundles, spine_seed=0, seed=1)
+    ly = synth.fiber_labels(n_at, args.bundles)
     x = np.concatenate([synth.random_orientations(synth.fibers(n, args.bundles, spine_seed=0,
                                                                seed=2), 20, seed=3),
                         synth.outlier_fibers(nout, seed=4)])
     lx = np.concatenate([synth.fiber_labels(n, args.bundles), -np.ones(nout, np.int32)])
-    a, b = synth.uniform_weights(len(x)), synth.uniform_weights(n)
+    a, b = synth.uniform_weights(len(x)), synth.uniform_weights(n_at)
     X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
     LY = torch.as_tensor(ly, dtype=torch.int32).cuda()
-    kw = dict(blur=1.0, reach=20.0, flip_points=20, multiscale=True, tol=0.0,
+    kw = dict(blur=blur, reach=20.0, flip_points=20, multiscale=True, tol=0.0,
               precision="bf16x3", stats=True)
     dt, (lab, score, st) = _timed(lambda: skh.label_transfer(X, A, Y, B, LY, args.bundles, **kw),
                                   args.steps, args.warmup)
     lab, score = lab.cpu().numpy(), score.cpu().numpy()
     inl = lx >= 0
     out = {"metric": f"time to soft labels, {n}-fibre subject (+1 % outliers, flips) from a "
-                     f"{n}-fibre atlas",
+                     f"{n_at}-fibre atlas",
            "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
            "config": {"workload": f"label transfer, {args.bundles} labelled bundles, 60-D fibres "
-                                  "stored in random directions, flip augmentation, blur 1 mm, "
+                                  "stored in random directions, flip augmentation, "
+                                  f"blur {blur:g} mm, "
                                   "reach 20 mm, scaling 0.9, multiscale, the Algorithm's "
                                   "schedule (one iteration per scale)"},
            "accuracy_inliers": float(np.mean(np.argmax(lab[inl], 1) == lx[inl])),
@@ -371,7 +378,7 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
     ap.add_argument("--workload", default="fibers200k",
                     choices=["fibers200k", "multiscale1m", "grad200k", "labels200k",
-                             "pcost200k", "barycenter10"])
+                             "labels250k", "pcost200k", "barycenter10"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison solve")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--bundles", type=int, default=50)
@@ -407,7 +414,7 @@ def main() -> int:
         return bench_multiscale(args, skh, synth)
     if args.workload == "grad200k":
         return bench_gradients(args, skh, synth)
-    if args.workload == "labels200k":
+    if args.workload in ("labels200k", "labels250k"):
         return bench_labels(args, skh, synth)
     if args.workload == "pcost200k":
         return bench_pcost(args, skh, synth)

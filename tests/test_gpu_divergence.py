@@ -154,6 +154,45 @@ def test_invalid_arguments():
         skh.sinkhorn_divergence(cuda(big), cuda(a[:10] * 5), cuda(big), cuda(a[:10] * 5), blur=0.1)
 
 
+def test_weight_failures_and_not_converged():
+    # NaN weight and zero total mass are argument errors; an iteration cap below what
+    # the tolerance needs returns valid results with converged = 0 (SKH_NOT_CONVERGED)
+    import ctypes
+
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd import _lib
+    x, a, y, b = synth.blob_pair(60, seed=16)
+    note("weight failures, not converged")
+    an = a.copy()
+    an[5] = np.nan
+    with pytest.raises(skh.SkhError) as e:
+        skh.sinkhorn_divergence(cuda(x), cuda(an), cuda(y), cuda(b), blur=0.1)
+    assert e.value.code == _lib.SKH_EINVAL
+    with pytest.raises(skh.SkhError) as e:
+        skh.sinkhorn_divergence(cuda(x), cuda(np.zeros_like(a)), cuda(y), cuda(b), blur=0.1)
+    assert e.value.code == _lib.SKH_EINVAL
+    S, pot, st = skh.sinkhorn_divergence(cuda(x), cuda(a), cuda(y), cuda(b), blur=0.01,
+                                         scaling=0.5, tol=1e-9, max_iters=3, potentials=True)
+    # max_iters counts the iterations at blur after the scale list
+    assert st["converged"] == 0 and st["iters"] == st["n_scales"] + 3
+    assert st["marginal_err"] > 1e-9
+    assert math.isfinite(S) and all(bool(v.isfinite().all()) for v in pot.values())
+    with pytest.raises(skh.SkhError) as e:  # empty cloud
+        skh.sinkhorn_divergence(cuda(x[:0]), cuda(a[:0]), cuda(y), cuda(b), blur=0.1)
+    assert e.value.code == _lib.SKH_EINVAL
+    # the C entry itself reports the positive status code
+    P = _lib.default_params()
+    P.blur, P.scaling, P.tol, P.max_iters = 0.01, 0.5, 1e-9, 3
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    out = ctypes.c_double()
+    ctx = skh._Ctx.get(X.device)
+    rc = _lib.load().skh_sinkhorn_divergence(ctx, X.data_ptr(), A.data_ptr(), len(x),
+                                             Y.data_ptr(), B.data_ptr(), len(y), x.shape[1],
+                                             ctypes.byref(P), ctypes.byref(out), None, None, None,
+                                             None, None)
+    assert rc == _lib.SKH_NOT_CONVERGED and math.isfinite(out.value)
+
+
 # ------------------------------------------------------------- BF16 split ---
 
 def test_fiber_downscaled_bf16_split():
