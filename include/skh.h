@@ -145,6 +145,15 @@ void skh_destroy(skh_ctx *ctx);
 int skh_set_stream(skh_ctx *ctx, void *hip_stream);
 /* Message of the last error on this context (ctx may be NULL: last create error). */
 const char *skh_last_error(const skh_ctx *ctx);
+/* Caps the device workspace this context may hold at `bytes` (0: no cap, the
+ * default).  A call whose workspace would exceed the cap fails with SKH_ENOMEM
+ * before the workspace grows (earlier launches of that call may have run; its
+ * outputs are then undefined) and leaves the context usable.  Setting a cap
+ * below the current holding synchronizes the stream and frees the workspace.
+ * Returns SKH_OK, SKH_EINVAL (NULL ctx) or SKH_EHIP. */
+int skh_set_workspace_limit(skh_ctx *ctx, size_t bytes);
+/* Device workspace bytes the context holds now (*out). */
+int skh_workspace_bytes(const skh_ctx *ctx, size_t *out);
 
 /*
  * One softmin, the reduction behind each of the four updates of the

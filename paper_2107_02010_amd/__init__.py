@@ -22,7 +22,7 @@ from ._lib import SkhError, SKH_FP32, SKH_BF16_SPLIT, SKH_FIX_P, SKH_FIX_Q, SKH_
 __all__ = ["softmin", "sinkhorn_divergence", "kmeans", "plan_apply", "grad_x", "gradients",
            "label_transfer", "sinkhorn_divergence_batched",
            "diameter",
-           "self_potential",
+           "self_potential", "set_workspace_limit", "workspace_bytes",
            "SinkhornDivergence", "sinkhorn_loss", "SkhError", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -286,6 +286,33 @@ def sinkhorn_divergence_batched(xs, as_, ys, bs, blur: float = 0.05, reach=None,
     pot = dict(f=list(torch.split(f, xn)), g=list(torch.split(g, yn)),
                p=list(torch.split(p, xn)), q=list(torch.split(q, yn)))
     return vals, pot, st.as_dict()
+
+
+def _device(device):
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    device = torch.device(device)
+    if device.type != "cuda":
+        raise ValueError("device must be a CUDA (HIP) device")
+    return device
+
+
+def set_workspace_limit(nbytes: int, device=None) -> None:
+    """Caps the device workspace of the library's context on `device` (0: no cap).  A call
+    that would need more raises SkhError (SKH_ENOMEM); a cap below the current holding
+    frees the workspace."""
+    if int(nbytes) < 0:
+        raise ValueError("nbytes must be >= 0")
+    ctx = _Ctx.get(_device(device))
+    _lib.check(_lib.load().skh_set_workspace_limit(ctx, int(nbytes)), ctx)
+
+
+def workspace_bytes(device=None) -> int:
+    """Device workspace bytes the library's context on `device` holds now."""
+    ctx = _Ctx.get(_device(device))
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().skh_workspace_bytes(ctx, ctypes.byref(out)), ctx)
+    return int(out.value)
 
 
 def diameter(x, y) -> float:

@@ -75,6 +75,8 @@ SIGNATURES = {
     "skh_destroy": (None, [_c_vp]),
     "skh_set_stream": (_c_i32, [_c_vp, _c_vp]),
     "skh_last_error": (ctypes.c_char_p, [_c_vp]),
+    "skh_set_workspace_limit": (_c_i32, [_c_vp, ctypes.c_size_t]),
+    "skh_workspace_bytes": (_c_i32, [_c_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "skh_softmin": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _c_d, _c_d,
                              _c_i32, _c_vp]),
     "skh_sinkhorn_divergence": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32,

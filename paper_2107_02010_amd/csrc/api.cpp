@@ -174,6 +174,27 @@ const char *skh_last_error(const skh_ctx *ctx) {
     return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
 
+int skh_set_workspace_limit(skh_ctx *ctx, size_t bytes) {
+    if (!ctx) return SKH_EINVAL;
+    ctx->ws_limit = bytes;
+    if (bytes && ws_total(ctx) > bytes) {  // release what the new limit does not cover
+        DeviceGuard guard(ctx->device);
+        SKH_HIP(hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < 4; ++k) {
+            if (ctx->ws[k]) SKH_HIP(hipFree(ctx->ws[k]));
+            ctx->ws[k] = nullptr;
+            ctx->ws_bytes[k] = 0;
+        }
+    }
+    return SKH_OK;
+}
+
+int skh_workspace_bytes(const skh_ctx *ctx, size_t *out) {
+    if (!ctx || !out) return SKH_EINVAL;
+    *out = ws_total(ctx);
+    return SKH_OK;
+}
+
 int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
                 const float *w, const float *h, double eps, double lam, int32_t precision,
                 float *out) {

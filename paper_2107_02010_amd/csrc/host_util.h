@@ -17,6 +17,7 @@ struct skh_ctx {
     // setup, loop, warm-start network, label-transfer buffers
     void *ws[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t ws_bytes[4] = {0, 0, 0, 0};
+    size_t ws_limit = 0;   // cap on the sum of ws_bytes (0: none)
     void *host = nullptr;  // pinned, kHostBytes
     int num_cus = 256;
     std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches
@@ -65,15 +66,29 @@ struct Carver {
     }
 };
 
+inline size_t ws_total(const skh_ctx *ctx) {
+    size_t t = 0;
+    for (size_t b : ctx->ws_bytes) t += b;
+    return t;
+}
+
 inline int ensure_ws(skh_ctx *ctx, int slot, size_t bytes) {
     if (bytes <= ctx->ws_bytes[slot]) return SKH_OK;
+    size_t want = bytes + bytes / 8;  // headroom against regrowth
+    if (ctx->ws_limit) {  // checked before anything is freed: the context stays usable
+        const size_t others = ws_total(ctx) - ctx->ws_bytes[slot];
+        if (others + bytes > ctx->ws_limit)
+            return fail(ctx, SKH_ENOMEM,
+                        "workspace limit of " + std::to_string(ctx->ws_limit) + " bytes: " +
+                            std::to_string(others + bytes) + " needed");
+        want = std::min(want, ctx->ws_limit - others);
+    }
     SKH_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->ws[slot]) {
         SKH_HIP(hipFree(ctx->ws[slot]));
         ctx->ws[slot] = nullptr;
         ctx->ws_bytes[slot] = 0;
     }
-    size_t want = bytes + bytes / 8;
     if (hipMalloc(&ctx->ws[slot], want) != hipSuccess) {
         (void)hipGetLastError();
         ctx->ws[slot] = nullptr;

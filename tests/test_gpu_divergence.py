@@ -220,3 +220,29 @@ def test_edge_sizes_bf16(n, m, d):
     b = synth.random_weights(m, 2)
     _compare(x, a, y, b, blur=0.1 * math.sqrt(d), reach=None, scaling=0.6, extra=2,
              precision="bf16x3")
+
+
+def test_workspace_limit():
+    # a cap below what a solve needs fails with SKH_ENOMEM before the workspace grows and
+    # leaves the context usable; without the cap the same solve runs
+    import paper_2107_02010_amd as skh
+    from paper_2107_02010_amd import _lib
+    x, a, y, b = synth.blob_pair(3000, seed=17)
+    X, A, Y, B = cuda(x), cuda(a), cuda(y), cuda(b)
+    note("workspace limit")
+    try:
+        skh.set_workspace_limit(64 << 10)  # 64 KiB: a larger holding is freed
+        assert skh.workspace_bytes() <= 64 << 10
+        with pytest.raises(skh.SkhError) as e:
+            skh.sinkhorn_divergence(X, A, Y, B, blur=0.05)
+        assert e.value.code == _lib.SKH_ENOMEM and "workspace limit" in str(e.value)
+        assert skh.workspace_bytes() <= 64 << 10
+        skh.set_workspace_limit(0)
+        S0 = skh.sinkhorn_divergence(X, A, Y, B, blur=0.05)
+        held = skh.workspace_bytes()
+        assert held > 64 << 10
+        skh.set_workspace_limit(held)  # enough: the same solve runs within it
+        assert skh.sinkhorn_divergence(X, A, Y, B, blur=0.05) == S0
+        assert skh.workspace_bytes() <= held
+    finally:
+        skh.set_workspace_limit(0)
