@@ -3,7 +3,7 @@
 The network is the learned warm start of the solver: a permutation-equivariant
 set encoder over coarse-cluster tokens that predicts, for every cluster of the
 two clouds, its (cross, self) dual values divided by blur^2.  It is not in the
-paper; the paper's Algorithm is the cold start it accelerates and the judge of
+paper; the paper's Algorithm is the cold start it accelerates and what decides
 its fixed point.  This module writes the same computation as the HIP kernels
 in plain numpy FP64 (library matrix products as steps), with a hand-derived
 backward pass, so that the kernels can be checked against it and it can be

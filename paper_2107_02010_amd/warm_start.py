@@ -1,7 +1,7 @@
 """Learned warm start of the symmetric Sinkhorn loop.
 
 Not part of the paper's method: the Algorithm (eps-scaling from the largest
-scale) stays the cold start, the fallback and the judge of the fixed point.  A
+scale) stays the cold start, the fallback and what decides the fixed point.  A
 set encoder reads one token per K-means cluster of each cloud (the coarse scale
 of Section 2's coarse-to-fine strategy) and predicts the cluster's mean cross
 dual and self dual, divided by blur^2.  Broadcast to the points, these are the
