@@ -73,8 +73,9 @@ def test_label_transfer_multiscale_fibres():
     assert np.all(score[inl] > 0.5)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("theta", [20.0, 0.0])
-def test_label_transfer_multiscale_plan_matches_dense(theta):
+def test_label_transfer_multiscale_plan_matches_dense(theta, precision):
     # The multiscale path applies the plan over the cluster blocks kept at the final
     # potentials (theta <= 0 keeps every block); the dense plan on the same potentials
     # (the solve is deterministic: same inputs, same vectors) differs by the dropped
@@ -84,8 +85,8 @@ def test_label_transfer_multiscale_plan_matches_dense(theta):
     import paper_2107_02010_amd as skh
     x, a, y, b, ly, lx = _case(2500, 3100, 5, 37, 4, seed=80)
     kw = dict(blur=1.0, reach=20.0, scaling=0.7, multiscale=True, trunc_theta=theta,
-              n_clusters=24, tol=0.0)
-    note(f"label transfer multiscale plan vs dense theta={theta}")
+              n_clusters=24, tol=0.0, precision=precision)
+    note(f"label transfer multiscale plan vs dense theta={theta} {precision}")
     lab, score = skh.label_transfer(cuda(x), cuda(a), cuda(y), cuda(b), _labels(ly), 5,
                                     flip_points=4, **kw)
     xa = np.ascontiguousarray(np.concatenate([x, oracle.flip_fibers(x, 4)]), np.float32)
