@@ -36,8 +36,11 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
     constexpr int VSTRIDE = LP >= 32 ? LP + 8 : LP + 4;
     constexpr bool kMfmaValues = LP >= 32;
     constexpr int NT2 = kMfmaValues ? LP / 32 : 1;  // 32-wide value tiles
-    __shared__ __attribute__((aligned(16))) float tile[kColsPerTile * STRIDE];
-    __shared__ __attribute__((aligned(16))) float vtile[kColsPerTile * VSTRIDE];
+    // columns per LDS tile: 128, or 64 when 128 would take more than 40 KB of LDS, so
+    // that four workgroups (four waves per SIMD) fit the 160 KB of a CU
+    constexpr int TC = (STRIDE + VSTRIDE) * 4 * kColsPerTile > 40 * 1024 ? 64 : kColsPerTile;
+    __shared__ __attribute__((aligned(16))) float tile[TC * STRIDE];
+    __shared__ __attribute__((aligned(16))) float vtile[TC * VSTRIDE];
 
     const int wg = blockIdx.x;
     int q = 0;
@@ -104,16 +107,16 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
         c_begin = rng[ri].x;
         c_end = rng[ri].y;
     }
-    for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
+    for (int j0 = c_begin; j0 < c_end; j0 += TC) {
         __syncthreads();
-        for (int e = tid; e < kColsPerTile * V4; e += 256) {
+        for (int e = tid; e < TC * V4; e += 256) {
             const int c = e / V4, v = e - c * V4;
             const int j = j0 + c;
             float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < c_end) val = *reinterpret_cast<const float4 *>(cols + (size_t)j * KP + v * 4);
             *reinterpret_cast<float4 *>(&tile[c * STRIDE + v * 4]) = val;
         }
-        for (int e = tid; e < kColsPerTile * LP; e += 256) {
+        for (int e = tid; e < TC * LP; e += 256) {
             const int c = e / LP, l = e - c * LP;
             const int j = j0 + c;
             float val = 0.0f;
@@ -121,12 +124,12 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
             vtile[c * VSTRIDE + l] = val;
         }
         __syncthreads();
-        if (tid < kColsPerTile) {  // augmented coordinate: the column offset
+        if (tid < TC) {  // augmented coordinate: the column offset
             const int j = j0 + tid;
             tile[tid * STRIDE + d] = j < c_end ? u[j] : ninf();
         }
         __syncthreads();
-        const int nblk = min(kColsPerTile / 32, (c_end - j0 + 31) >> 5);
+        const int nblk = min(TC / 32, (c_end - j0 + 31) >> 5);
         for (int jb = 0; jb < nblk; ++jb) {
             v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
