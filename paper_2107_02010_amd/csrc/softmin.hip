@@ -70,7 +70,10 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
     constexpr int H = KP / 2;      // k-steps per 32x32 block; lane half h holds dims [h*H, h*H+H)
     constexpr int STRIDE = KP + 4; // LDS row stride (floats)
     constexpr int V4 = KP / 4;     // float4 per packed point
-    __shared__ __attribute__((aligned(16))) float tile[kColsPerTile * STRIDE];
+    // columns per LDS tile: 64 for wide points (17 KB instead of 35 KB of LDS, so the
+    // CU holds more than four workgroups), 128 otherwise
+    constexpr int TC = KP >= 32 ? 64 : kColsPerTile;
+    __shared__ __attribute__((aligned(16))) float tile[TC * STRIDE];
 
     const int wg = blockIdx.x;
     int q = 0;
@@ -152,9 +155,9 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         c_begin = r.x;
         c_end = r.y;
     }
-    for (int j0 = c_begin; j0 < c_end; j0 += kColsPerTile) {
+    for (int j0 = c_begin; j0 < c_end; j0 += TC) {
         __syncthreads();
-        for (int e = tid; e < kColsPerTile * V4; e += 256) {
+        for (int e = tid; e < TC * V4; e += 256) {
             const int c = e / V4, v = e - c * V4;
             const int j = j0 + c;
             float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
         }
         __syncthreads();
         const int nvalid = c_end - j0;
-        const int nblk = wave_active ? min(kColsPerTile / 32, (nvalid + 31) >> 5) : 0;
+        const int nblk = wave_active ? min(TC / 32, (nvalid + 31) >> 5) : 0;
         for (int jb = 0; jb < nblk; ++jb) {
             const float *tp = &tile[(jb * 32 + li) * STRIDE + h * H];
             v16f acc = __builtin_amdgcn_mfma_f32_32x32x2f32(tp[0], xr[0], base, 0, 0, 0);
