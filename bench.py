@@ -69,7 +69,7 @@ def read_traffic(precision: str):
         return None
     txt = open(TRAFFIC_FILE).read()
     m = re.search(rf"kernel_sha256_16\[{precision}\]:\s*([0-9a-f]+)", txt)
-    t = re.search(rf"bytes_per_launch\[{precision}\]:\s*([0-9.eE+]+)", txt)
+    t = re.search(rf"^bytes_per_launch\[{precision}\]:\s*([0-9.eE+]+)", txt, flags=re.M)
     if not m or not t or m.group(1) != kernel_hash(precision):
         return None
     return float(t.group(1))
