@@ -267,7 +267,7 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     batch.kscale = (float)(kLog2e / eps);
     batch.job[0].n_rows = (int)n;
     batch.job[0].n_cols = m_cols;
-    const int wgs = skh::plan_softmin_batch(batch, split ? target_wgs_split(ctx) : target_wgs(ctx));
+    const int wgs = skh::plan_softmin_batch(batch, target_wgs_softmin(ctx, split));
     float *u, *hperm;
     float2 *part;
     for (int pass = 0; pass < 2; ++pass) {
@@ -654,7 +654,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
             batch.job[k].range_count = seg_ones;
         }
     }
-    const int wgs = skh::plan_softmin_batch(batch, split ? target_wgs_split(ctx) : target_wgs(ctx));
+    const int wgs = skh::plan_softmin_batch(batch, target_wgs_softmin(ctx, split));
     const int fbx = skh::finish_blocks(nn), fby = skh::finish_blocks(mm);
     // coarse loop and jump batches (multiscale)
     skh::SoftminBatch cbatch{}, jbatch{};

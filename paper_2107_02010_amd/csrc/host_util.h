@@ -124,11 +124,14 @@ inline std::vector<double> scale_list(double diameter, double blur, double scali
 }
 
 inline int target_wgs(const skh_ctx *ctx) { return ctx->num_cus * 8; }
-// The BF16 split softmin holds three workgroups per CU, each working for milliseconds
-// on a full column sweep: splitting the columns into more chunks (about 21 rounds of
-// the resident workgroups at the 200k-fibre shape instead of 8) shortens the last,
-// partly idle round.
-inline int target_wgs_split(const skh_ctx *ctx) { return ctx->num_cus * 64; }
+// Workgroup target of the fine-loop softmin launches.  A workgroup sweeps a whole column
+// chunk for milliseconds; splitting the columns into more chunks (at the 200k-point
+// shape: three for the BF16 split kernel, three resident workgroups per CU; four for
+// the FP32 kernel) gives many rounds of resident workgroups, so the last, partly idle
+// round costs little.
+inline int target_wgs_softmin(const skh_ctx *ctx, bool split) {
+    return ctx->num_cus * (split ? 64 : 96);
+}
 
 inline int ensure_events(skh_ctx *ctx, size_t count) {
     while (ctx->events.size() < count) {
