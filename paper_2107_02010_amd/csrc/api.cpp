@@ -1119,7 +1119,8 @@ int run_plans(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d
         batch.job[k].n_cols = (int)specs[k].m;
         batch.job[k].L = specs[k].L;
     }
-    const int wgs = skh::plan_plan_batch(batch, target_wgs(ctx));
+    // many rounds of resident workgroups (four per CU): the last, partly idle one is short
+    const int wgs = skh::plan_plan_batch(batch, ctx->num_cus * 96);
     float *Xp, *hnx, *plo, *phi, *lohi, *Cp[2], *hnc[2], *lwc[2], *uc[2], *part[2];
     double *pmass, *mass;
     int *pbad, *bad;
