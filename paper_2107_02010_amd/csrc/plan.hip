@@ -313,6 +313,8 @@ hipError_t launch_plan_weighted(const PlanBatch &b, int kp, int lp, int total_wg
 // Merges chunk records [M, W, P_0..P_{L-1}] of one job into
 //   out_il = scale_i 2^{c_i + M_i} P_il,  c_i = log2(e) (pot_i - hn_i) / eps,
 // scale_i = w_i (or 1), and mass_i = scale_i 2^{c_i + M_i} W_i when mass != NULL.
+// One factor 2^{M_c - M} per chunk; the value sums (LP >= L of them) stay in registers.
+template <int LP>
 __global__ __launch_bounds__(256) void k_plan_finish(const float *__restrict__ part, int chunks,
                                                      int n, int L, const float *__restrict__ hn,
                                                      const float *__restrict__ pot,
@@ -328,30 +330,37 @@ __global__ __launch_bounds__(256) void k_plan_finish(const float *__restrict__ p
     double base = 0.0;
     if (M > ninf())
         base = scale * exp2(1.4426950408889634074 * ((double)pot[i] - (double)hn[i]) / eps + (double)M);
-    double W = 0.0;
-    for (int l = 0; l < L; ++l) {
-        double acc = 0.0;
-        for (int c = 0; c < chunks; ++c) {
-            const float *rec = part + ((size_t)c * n + i) * RW;
-            if (rec[0] > ninf()) acc += (double)rec[2 + l] * exp2((double)rec[0] - (double)M);
-        }
-        out[(size_t)i * L + l] = (float)(base * acc);
+    double acc[LP], W = 0.0;
+#pragma unroll
+    for (int l = 0; l < LP; ++l) acc[l] = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        const float *rec = part + ((size_t)c * n + i) * RW;
+        if (!(rec[0] > ninf())) continue;
+        const double f = exp2((double)rec[0] - (double)M);
+#pragma unroll
+        for (int l = 0; l < LP; ++l)
+            if (l < L) acc[l] += (double)rec[2 + l] * f;
+        W += (double)rec[1] * f;
     }
-    if (mass) {
-        for (int c = 0; c < chunks; ++c) {
-            const float *rec = part + ((size_t)c * n + i) * RW;
-            if (rec[0] > ninf()) W += (double)rec[1] * exp2((double)rec[0] - (double)M);
-        }
-        mass[i] = (float)(base * W);
-    }
+#pragma unroll
+    for (int l = 0; l < LP; ++l)
+        if (l < L) out[(size_t)i * L + l] = (float)(base * acc[l]);
+    if (mass) mass[i] = (float)(base * W);
 }
 
 hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const float *hn,
                               const float *pot, const float *w, double eps, float *out,
                               float *mass, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan_finish, dim3((n + 255) / 256), dim3(256), 0, s, part, chunks, n, L, hn,
-                       pot, w, eps, out, mass);
+    const dim3 grid((n + 255) / 256), block(256);
+    switch (plan_value_width(L)) {
+    case 4: hipLaunchKernelGGL(k_plan_finish<4>, grid, block, 0, s, part, chunks, n, L, hn, pot, w, eps, out, mass); break;
+    case 8: hipLaunchKernelGGL(k_plan_finish<8>, grid, block, 0, s, part, chunks, n, L, hn, pot, w, eps, out, mass); break;
+    case 16: hipLaunchKernelGGL(k_plan_finish<16>, grid, block, 0, s, part, chunks, n, L, hn, pot, w, eps, out, mass); break;
+    case 32: hipLaunchKernelGGL(k_plan_finish<32>, grid, block, 0, s, part, chunks, n, L, hn, pot, w, eps, out, mass); break;
+    case 64: hipLaunchKernelGGL(k_plan_finish<64>, grid, block, 0, s, part, chunks, n, L, hn, pot, w, eps, out, mass); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
