@@ -264,6 +264,8 @@ int plan_plan_batch(PlanBatch &b, int target_wgs) {
     }
     int want_chunks = row_tiles_total > 0 ? (target_wgs + row_tiles_total - 1) / row_tiles_total : 1;
     if (want_chunks < 1) want_chunks = 1;
+    // each chunk holds L + 2 floats per row and the merge walks them per row
+    if (want_chunks > 64) want_chunks = 64;
     int total = 0;
     for (int q = 0; q < b.n_jobs; ++q) {
         PlanJob &J = b.job[q];
