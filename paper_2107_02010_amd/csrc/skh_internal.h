@@ -40,11 +40,11 @@ struct SoftminJob {
     int n_chunks;       // column chunks
     int chunk_cols;     // columns per chunk (multiple of kColsPerTile)
     int wg_begin;       // first workgroup of this job in the launch
-    // Block-sparse mode (tiles != NULL): workgroup w handles tiles[w] =
+    // Block-sparse mode (tiles != NULL): workgroup w handles tiles[w % n_tiles] =
     // {row_begin, row_end, row_cluster, 0} (rows of one cluster, at most
     // kRowsPerBlock) against the column ranges ranges[cluster * range_cap ..
-    // + range_count[cluster]), each [begin, end) in padded column order; one
-    // chunk (n_chunks = 1).
+    // + range_count[cluster]), each [begin, end) in padded column order; chunk
+    // c = w / n_tiles takes ranges c, c + n_chunks, ... of that list.
     const int4 *tiles;
     const int2 *ranges;
     const int *range_count;

@@ -91,17 +91,19 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
     const float kscale = B.kscale;
 
     // rows [rb, re) and the column ranges of this workgroup
-    int rb, re, chunk, nranges, cl_row = 0;
+    int rb, re, chunk, nranges, cl_row = 0, r0 = 0, rstep = 1;
     const int2 *rng = nullptr;
     int c_begin = 0, c_end = 0;
-    if (J.tiles) {
-        const int4 t = J.tiles[local];
+    if (J.tiles) {  // chunk c of a row tile takes its ranges c, c + n_chunks, ...
+        const int4 t = J.tiles[local % J.n_tiles];
         rb = t.x;
         re = t.y;
         cl_row = t.z;
-        chunk = 0;
+        chunk = local / J.n_tiles;
         rng = J.ranges + (size_t)cl_row * J.range_cap;
         nranges = J.range_count[cl_row];
+        r0 = chunk;
+        rstep = J.n_chunks;
     } else {
         const int rt = local % J.row_tiles;
         chunk = local / J.row_tiles;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) base[r] = kLevel ? -R : 0.0f;
 
-    for (int ri = 0; ri < nranges; ++ri) {
+    for (int ri = r0; ri < nranges; ri += rstep) {
     if (rng) {
         const int2 r = rng[ri];
         c_begin = r.x;
@@ -266,14 +268,21 @@ int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
     }
     int want_chunks = row_tiles_total > 0 ? (target_wgs + row_tiles_total - 1) / row_tiles_total : 1;
     if (want_chunks < 1) want_chunks = 1;
+    // block-sparse jobs: split each row tile's column ranges over up to four workgroups
+    // when the row tiles alone give few rounds of resident workgroups
+    int tiles_total = 0;
+    for (int q = 0; q < b.n_jobs; ++q)
+        if (b.job[q].tiles) tiles_total += b.job[q].n_tiles;
+    int tile_chunks = tiles_total > 0 ? (target_wgs + tiles_total - 1) / tiles_total : 1;
+    tile_chunks = tile_chunks < 1 ? 1 : (tile_chunks > 4 ? 4 : tile_chunks);
     int total = 0;
     for (int q = 0; q < b.n_jobs; ++q) {
         SoftminJob &J = b.job[q];
-        if (J.tiles) {  // block-sparse: one workgroup per row tile, one chunk
+        if (J.tiles) {  // block-sparse: workgroups per row tile = chunks of its range list
             J.chunk_cols = 0;
-            J.n_chunks = 1;
+            J.n_chunks = J.range_cap > 1 ? tile_chunks : 1;
             J.wg_begin = total;
-            total += J.n_tiles;
+            total += J.n_tiles * J.n_chunks;
             continue;
         }
         int tiles = (J.n_cols + kColsPerTile - 1) / kColsPerTile;

@@ -94,16 +94,18 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     const float kscale = B.kscale;
 
     // rows [rb, re) and the column ranges of this workgroup
-    int rb, re, chunk, nranges;
+    int rb, re, chunk, nranges, r0 = 0, rstep = 1;
     const int2 *rng = nullptr;
     int c_begin = 0, c_end = 0;
-    if (J.tiles) {
-        const int4 t = J.tiles[local];
+    if (J.tiles) {  // chunk c of a row tile takes its ranges c, c + n_chunks, ...
+        const int4 t = J.tiles[local % J.n_tiles];
         rb = t.x;
         re = t.y;
-        chunk = 0;
+        chunk = local / J.n_tiles;
         rng = J.ranges + (size_t)t.z * J.range_cap;
         nranges = J.range_count[t.z];
+        r0 = chunk;
+        rstep = J.n_chunks;
     } else {
         const int rt = local % J.row_tiles;
         chunk = local / J.row_tiles;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
             a += kColsPerTile;
             return true;
         }
-        for (++r; r < nranges; ++r) {
+        for (r = r < 0 ? r0 : r + rstep; r < nranges; r += rstep) {
             const int2 v = rng ? rng[r] : make_int2(c_begin, c_end);
             if (v.x < v.y) {
                 a = v.x;
