@@ -708,7 +708,7 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
             pairs_ctr = c.take<unsigned long long>(1);
             if (pp) {
                 pp_V = c.take<float>((size_t)cy.n_pad * pp->L);
-                pp_part = c.take<float>((size_t)cx.n_pad * (pp->L + 2));
+                pp_part = c.take<float>((size_t)skh::kMaxPlanTileChunks * cx.n_pad * (pp->L + 2));
                 pp_out = c.take<float>((size_t)cx.n_pad * pp->L);
             }
             if (t_jump > 0) {
@@ -1045,10 +1045,10 @@ static int solve(skh_ctx *ctx, const float *x, const float *a, int64_t n, const 
         PJ.ranges = ranges[3];
         PJ.range_count = rcount[3];
         PJ.range_cap = batch.job[3].range_cap;
-        const int pwgs = skh::plan_plan_batch(pb, target_wgs(ctx));
+        const int pwgs = skh::plan_plan_batch(pb, ctx->num_cus * 32);
         SKH_HIP(skh::launch_plan_weighted(pb, kp, pp_lp, pwgs, s));
-        SKH_HIP(skh::launch_plan_finish(pp_part, 1, (int)cx.n_pad, pp->L, cx.hn, F, nullptr,
-                                        eps_blur, pp_out, nullptr, s));
+        SKH_HIP(skh::launch_plan_finish(pp_part, PJ.n_chunks, (int)cx.n_pad, pp->L, cx.hn, F,
+                                        nullptr, eps_blur, pp_out, nullptr, s));
         SKH_HIP(skh::launch_unpermute_rows(pp_out, cx.perm_pad, (int)cx.n_pad, pp->L, pp->out, s));
     }
     double ms_softmin = 0.0;

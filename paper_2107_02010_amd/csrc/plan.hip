@@ -61,13 +61,16 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
     int rb, re, chunk, nranges;
     const int2 *rng = nullptr;
     int c_begin = 0, c_end = 0;
-    if (J.tiles) {
-        const int4 t = J.tiles[local];
+    int r0 = 0, rstep = 1;
+    if (J.tiles) {  // chunk c of a row tile takes its ranges c, c + n_chunks, ...
+        const int4 t = J.tiles[local % J.n_tiles];
         rb = t.x;
         re = t.y;
-        chunk = 0;
+        chunk = local / J.n_tiles;
         rng = J.ranges + (size_t)t.z * J.range_cap;
         nranges = J.range_count[t.z];
+        r0 = chunk;
+        rstep = J.n_chunks;
     } else {
         const int rt = local % row_tiles;
         chunk = local / row_tiles;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void k_plan_weighted(const PlanBatch B) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) pacc[t][r] = 0.0f;
 
-    for (int ri = 0; ri < nranges; ++ri) {
+    for (int ri = r0; ri < nranges; ri += rstep) {
     if (rng) {
         c_begin = rng[ri].x;
         c_end = rng[ri].y;
@@ -251,14 +254,18 @@ int plan_plan_batch(PlanBatch &b, int target_wgs) {
     }
     bool sparse = false;
     for (int q = 0; q < b.n_jobs; ++q) sparse = sparse || b.job[q].tiles != nullptr;
-    if (sparse) {  // block-sparse: one workgroup per row tile, one chunk
+    if (sparse) {  // block-sparse: each row tile's range list over up to kMaxPlanTileChunks
+        int tiles_total = 0;
+        for (int q = 0; q < b.n_jobs; ++q) tiles_total += b.job[q].n_tiles;
+        int c = tiles_total > 0 ? (target_wgs + tiles_total - 1) / tiles_total : 1;
+        c = c < 1 ? 1 : (c > kMaxPlanTileChunks ? kMaxPlanTileChunks : c);
         int total = 0;
         for (int q = 0; q < b.n_jobs; ++q) {
             PlanJob &J = b.job[q];
             J.chunk_cols = 0;
-            J.n_chunks = 1;
+            J.n_chunks = J.range_cap > 1 ? c : 1;
             J.wg_begin = total;
-            total += J.n_tiles;
+            total += J.n_tiles * J.n_chunks;
         }
         return total;
     }

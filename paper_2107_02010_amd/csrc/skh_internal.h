@@ -99,6 +99,9 @@ struct PlanBatch {
 };
 int plan_plan_batch(PlanBatch &b, int target_wgs);
 int plan_value_width(int L);  // 4..64, 0 if L > 64
+// Block-sparse plan launches split a row tile's range list over at most this many
+// workgroups (records per row: that many times L + 2 floats).
+constexpr int kMaxPlanTileChunks = 4;
 hipError_t launch_plan_weighted(const PlanBatch &b, int kp, int lp, int total_wgs, hipStream_t s);
 hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const float *hn,
                               const float *pot, const float *w, double eps, float *out,
