@@ -35,7 +35,8 @@ __global__ __launch_bounds__(256) void k_kmeans_assign(const float *__restrict__
                                                        int *__restrict__ label) {
     constexpr int H = KP / 2;       // k-steps per block; lane half h holds slots [h H, h H + H)
     constexpr int STRIDE = KP + 4;  // LDS row stride (floats)
-    constexpr int TCN = 128;        // centres per tile
+    // centres per tile: 64 for wide points (17 KB of LDS, six workgroups per CU), else 128
+    constexpr int TCN = KP >= 32 ? 64 : 128;
     __shared__ float tile[TCN * STRIDE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, li = lane & 31;
