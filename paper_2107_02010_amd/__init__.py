@@ -459,6 +459,10 @@ class SinkhornDivergence(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, a, y, b, kw):
+        if float(kw.get("p", 2.0)) != 2.0 and any(ctx.needs_input_grad[:4]):
+            # the gradient kernels implement the cost |x - y|^2 / 2 only; refuse rather
+            # than return the gradient of another problem
+            raise ValueError("gradients of S are implemented for the cost exponent p = 2 only")
         S, pot, st = sinkhorn_divergence(x, a, y, b, potentials=True, **kw)
         ctx.save_for_backward(x, a, y, b, pot["f"], pot["g"], pot["p"], pot["q"])
         ctx.blur = kw.get("blur", 0.05)
