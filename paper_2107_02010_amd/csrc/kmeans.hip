@@ -1,5 +1,5 @@
-// K-means coarse scale and the cluster-sorted layout (coarse-to-fine strategy,
-// Section 2: "a simple K-means algorithm" for the coarse subsampling).
+// K-means coarse scale and the cluster-sorted layout (Section 2, coarse-to-fine
+// strategy: the coarse measures are K-means clusterings of the two clouds).
 //
 // Lloyd iterations on the device:
 //   assign   label_i = argmin_c |c|^2/2 - <x_i, c>     (ties -> lowest c)
@@ -24,8 +24,9 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // distance is ranked by 1/2 |c|^2 - <x, c> (the |x|^2 term is common to a row),
 // computed on the matrix cores like the softmin's contraction: each wave keeps
 // 32 rows as the B operand of v_mfma_f32_32x32x2f32 in VGPRs, with the unused
-// last slot set to 1; tiles of 128 centres are staged in LDS as -c with
-// 1/2 |c|^2 in that slot, so the MFMA output is the ranking value itself.
+// last slot set to 1; tiles of centres (64 for wide points, 128 otherwise) are
+// staged in LDS as -c with 1/2 |c|^2 in that slot, so the MFMA output is the
+// ranking value itself.
 // Each lane keeps the running minimum of its 16 centres per block; the two
 // lane halves of a row combine once at the end.  Rows padded to KP have their
 // slots past the coordinates at zero, so slot KP - 1 is free.

@@ -1,6 +1,7 @@
-// Coarse-to-fine support: cluster-block kernel truncation (Section 2,
-// coarse-to-fine strategy: the coarse dual vectors prune computations at full
-// resolution, the kernel truncation of Schmitzer) and the coarse measures.
+// Coarse-to-fine support (Section 2, coarse-to-fine strategy, which cites
+// Schmitzer's kernel truncation): a cluster block of the fine softmin is left
+// out when the current dual vectors bound all its weights below e^{-theta};
+// also the coarse measures of the K-means clusters.
 //
 // Truncation test for a row cluster I and a column cluster J, for the softmin
 // whose rows carry potential f (scaled by 1/lambda inside the softmin) and

@@ -58,6 +58,11 @@ struct SoftminBatch {
     int d;         // coordinates per point; slot d carries the augmented term
     float kscale;  // log2(e) / eps
     float cost_p;  // exponent p of the cost |x - y|^p / p; 0 or 2: the p = 2 kernels
+    // log2 of the largest term (relative to a row's level) that a skipped block may
+    // hold, set by plan_softmin_batch from the longest column set of the launch: with a
+    // row sum >= 2^-4 of the level, m such terms add less than 2^-28 m 2^skip_log2,
+    // below FP32 rounding when skip_log2 <= -28 - log2(m)
+    float skip_log2;
 };
 
 // Builds chunking for a batch of jobs so that the launch holds enough

@@ -34,12 +34,15 @@
 // that need it, only when a row's sum would leave [2^-4, 2^59) (first mass,
 // overflow): the new level is the larger of the block's maximum and the sum so
 // far, and the block is re-summed from the accumulators.  Once every row of a
-// wave holds mass, a block whose terms all lie below 2^-48 of the level is
-// skipped after its products (with the row sum >= 2^-4 of the level, a million
-// such blocks move it by less than FP32 rounding).
+// wave holds mass, a block whose terms all lie below 2^T of the level is
+// skipped after its products, T = min(-48, -28 - ceil(log2 m)) for m columns:
+// with the row sum >= 2^-4 of the level, all m columns of such terms move it by
+// less than FP32 rounding.
 //
 // Zero weights and the ragged column tail both enter as u_j = -inf, which the
 // contraction turns into s_ij = -inf and the exponential into 0.
+#include <algorithm>
+
 #include "skh_internal.h"
 
 namespace skh {
@@ -62,8 +65,6 @@ static __device__ __forceinline__ float row_max(float v) {
     const auto t = __builtin_amdgcn_permlane32_swap(w, w, false, false);
     return fmaxf(__uint_as_float(t[0]), __uint_as_float(t[1]));
 }
-// log2 of the largest term a skipped block may hold (relative to the level)
-constexpr float kNegligibleF32 = -48.0f;
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
                 float mx = acc[0];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
-                if (!__any(mx > kNegligibleF32)) continue;
+                if (!__any(mx > B.skip_log2)) continue;
             }
             float ex[16];
 #pragma unroll
@@ -259,7 +260,17 @@ __global__ __launch_bounds__(256) void k_softmin_f32(const SoftminBatch B) {
     }
 }
 
+// log2 bound of a skippable term for column sets of at most m points (see skip_log2)
+static float skip_threshold(int64_t m) {
+    int lg = 0;
+    while (lg < 62 && (int64_t(1) << lg) < m) ++lg;  // ceil(log2 m)
+    return (float)std::min(-48, -28 - lg);
+}
+
 int plan_softmin_batch(SoftminBatch &b, int target_wgs) {
+    int max_cols = 1;
+    for (int q = 0; q < b.n_jobs; ++q) max_cols = std::max(max_cols, b.job[q].n_cols);
+    b.skip_log2 = skip_threshold(max_cols);
     int row_tiles_total = 0;
     for (int q = 0; q < b.n_jobs; ++q) {
         SoftminJob &J = b.job[q];

@@ -31,9 +31,10 @@
 // so far sets the new level and the block is re-summed from the accumulators.
 // A row that holds mass keeps a sum >= 2^-4 (sums only grow; a cluster change
 // re-rounds the level by far less), so once every row of a wave holds mass the per-half
-// overflow test runs, and a block whose terms all lie below 2^-48 of the level
-// is skipped after its products (it cannot move any row sum beyond rounding);
-// the products of every pair are still computed.
+// overflow test runs, and a block whose terms all lie below 2^T of the level
+// (T = B.skip_log2: -48, lower for column sets beyond 2^20 points) is skipped
+// after its products (it cannot move any row sum beyond rounding); the products
+// of every pair are still computed.
 //
 // Padding and zero-weight columns use a finite sentinel (-1e30) rather than
 // -inf so that the lo products stay finite (-inf * 0 would be NaN).
@@ -45,9 +46,6 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kMasked = -1.0e30f;
-// log2 of the largest term a block may hold and still be skipped: with the row
-// sum >= 2^-4, a million columns of such terms move it by < 2^-24 relative.
-constexpr float kNegligible = -48.0f;
 
 static __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 static __device__ __forceinline__ float xor32_sum(float v) {
@@ -260,14 +258,14 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[s], acc, 0, 0, 0);
             }
             // acc[r] = s_ij - R.  Once every row of the wave holds mass (its sum is
-            // >= 2^-4 relative to R), a block whose terms are all below 2^kNegligible
+            // >= 2^-4 relative to R), a block whose terms are all below 2^skip_log2
             // cannot change any row sum beyond FP32 rounding: its exponentials are
             // skipped (wave-uniform test on the block maximum).
             if (all_mass) {
                 float mx = acc[0];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
-                if (!__any(mx > kNegligible)) continue;
+                if (!__any(mx > B.skip_log2)) continue;
             }
             // pairwise sum keeps the add chain short
             float ex[16];
