@@ -94,45 +94,119 @@ def test_softmin_fiber_full_size_sampled_rows():
 
 
 # ------------------------------------------------------------- BF16 split ---
+#
+# The split contraction of one pair errs by at most 3 * 2^-16 |k x_i| |y_j - c_J| in
+# log2 units (bf16 unit 2^-8: the dropped lo.lo product and the residuals of the two
+# splits), i.e. 3 * 2^-16 lam |x_i| |y_j - c_J| in cost units, and log-sum-exp is
+# 1-Lipschitz in the max norm, so a row errs by at most that for its worst column plus
+# the FP32 bound of the rest of the arithmetic.  c_J is the centre of column j's
+# K-means cluster.  For points inside the bounding box of the columns the library
+# centres both clouds on the midpoint of that box, exactly as skh.kmeans centres the
+# columns alone, so the clustering skh.kmeans returns (ceil(sqrt(m)) clusters, 10 Lloyd
+# steps, the same packed width at d = 60) is the one the split path uses.
+
+def _inside(x, y):
+    """x clipped into the bounding box of y (see above)."""
+    return np.clip(x, y.min(0), y.max(0)).astype(np.float32)
+
+
+def _offset_radius(y, w):
+    """max |y_j - c_J| over the columns with positive weight, from the clustering of
+    the split path (FP64, from the centres skh.kmeans returns)."""
+    import math
+
+    import paper_2107_02010_amd as skh
+    km = skh.kmeans(cuda(y), cuda(w), k=math.ceil(math.sqrt(len(y))), iters=10)
+    c = host(km["centres"])
+    lab = km["labels"].cpu().numpy()
+    off = np.linalg.norm(y.astype(np.float64) - c[lab], axis=1)
+    return float(off[w > 0].max())
+
+
+def _split_bound(xc_rows, radius, lam):
+    # 1.25: the FP32 rounding of the split terms themselves
+    return 1.25 * 3 * 2.0 ** -16 * lam * np.linalg.norm(xc_rows, axis=1) * radius
+
 
 def test_softmin_bf16_fiber_full_size_sampled_rows():
     # the benchmark's 200k x 200k fibre shape on the BF16 split path (its chosen
     # precision): sampled rows against all 200k columns in FP64, within the FP32 bound
-    # plus the split bound of _check_bf16 (any cluster centre lies in the cloud's hull)
+    # plus the split bound on the actual cluster offsets
     import paper_2107_02010_amd as skh
     from gpu_common import centred
     x, a, y, b = synth.fiber_pair(200_000, 50, seed=12)
+    x = _inside(x, y)
     rng = np.random.default_rng(8)
     h = (2.0 * rng.standard_normal(200_000)).astype(np.float32)
     rows = np.sort(rng.choice(200_000, size=64, replace=False))
     rows[-1] = 199_999
     xc, yc = centred(x, y)
+    note("softmin bf16 fibres 200k: column clustering")
+    radius = _offset_radius(y, b)
     for eps in (1.0, 400.0):
         note(f"softmin bf16 fibres 200k eps={eps}")
         out = host(skh.softmin(cuda(x), cuda(y), cuda(b), cuda(h), eps, 1.0,
                                precision="bf16x3"))
         ref = oracle.softmin(x[rows], y, b, h, eps, 1.0)
+        split = _split_bound(xc[rows], radius, 1.0)
+        # the split term is a small part of the scale of the problem
+        assert split.max() <= 0.05 * eps, (eps, radius, split.max())
         bound = softmin_fp32_bound(np.concatenate([x[rows], x]), y, b.astype(np.float64),
                                    h.astype(np.float64), eps, 1.0,
-                                   np.concatenate([ref, np.zeros(len(x))]))[:len(rows)]
-        bound += 8 * 3 * 2.0 ** -16 * np.linalg.norm(xc[rows], axis=1) * 2 * \
-            np.linalg.norm(yc, axis=1).max()
+                                   np.concatenate([ref, np.zeros(len(x))]))[:len(rows)] + split
         err = np.abs(out[rows] - ref)
+        print(f"bf16 200k eps={eps}: radius {radius:.3f}, max err {err.max():.3e}, "
+              f"max bound {bound.max():.3e} (split {split.max():.3e}), |out| >= "
+              f"{np.abs(ref).min():.3f}")
         assert np.all(np.isfinite(out))
         assert np.all(err <= bound), (eps, np.max(err / bound))
+        # a 1 % error of any sampled row is far outside what the kernel shows
+        assert np.all(err <= 1e-3 * np.abs(ref) + 1e-3 * eps), (eps, np.max(err / np.abs(ref)))
 
 
-def _check_bf16(x, y, w, h, eps, lam, tag):
-    """BF16 hi/lo split: the contraction error of one pair is at most
-    3 * 2^-16 |x_i| |y_j - c_J| (dropped lo.lo product and the two split residuals),
-    with |y_j - c_J| <= 2 max |y| for any cluster centre c_J inside the cloud's hull."""
+def test_softmin_bf16_fiber_1m_sampled_rows():
+    # 1M x 1M fibres (the time-to-S workload: 200 bundles, 1000 column clusters), one
+    # dense BF16 split launch, sampled rows against all 1M columns in FP64
+    import paper_2107_02010_amd as skh
+    from gpu_common import centred
+    x, a, y, b = synth.fiber_pair(1_000_000, 200, seed=0)
+    x = _inside(x, y)
+    rng = np.random.default_rng(10)
+    h = (2.0 * rng.standard_normal(len(y))).astype(np.float32)
+    rows = np.sort(rng.choice(len(x), size=24, replace=False))
+    rows[-1] = len(x) - 1
+    xc, yc = centred(x, y)
+    note("softmin bf16 fibres 1M: column clustering")
+    radius = _offset_radius(y, b)
+    eps = 1.0
+    note(f"softmin bf16 fibres 1M eps={eps}")
+    out = host(skh.softmin(cuda(x), cuda(y), cuda(b), cuda(h), eps, 1.0, precision="bf16x3"))
+    ref = oracle.softmin(x[rows], y, b, h, eps, 1.0)
+    split = _split_bound(xc[rows], radius, 1.0)
+    assert split.max() <= 0.05 * eps, (radius, split.max())
+    bound = softmin_fp32_bound(np.concatenate([x[rows], x]), y, b.astype(np.float64),
+                               h.astype(np.float64), eps, 1.0,
+                               np.concatenate([ref, np.zeros(len(x))]))[:len(rows)] + split
+    err = np.abs(out[rows] - ref)
+    print(f"bf16 1M: radius {radius:.3f}, max err {err.max():.3e}, max bound {bound.max():.3e}")
+    assert np.all(np.isfinite(out))
+    assert np.all(err <= bound), np.max(err / bound)
+    assert np.all(err <= 1e-3 * np.abs(ref) + 1e-3 * eps), np.max(err / np.abs(ref))
+
+
+def _check_bf16(x, y, w, h, eps, lam, tag, radius=None):
+    """BF16 hi/lo split against the oracle: the FP32 bound plus the split bound, on the
+    actual cluster offsets when `radius` is given (see _offset_radius), otherwise with
+    |y_j - c_J| <= 2 max |y| for any cluster centre c_J inside the cloud's hull."""
     import paper_2107_02010_amd as skh
     from gpu_common import centred
     note(f"softmin bf16 {tag} n={x.shape[0]} m={y.shape[0]} d={x.shape[1]} eps={eps}")
     out = host(skh.softmin(cuda(x), cuda(y), cuda(w), cuda(h), eps, lam, precision="bf16x3"))
     ref = oracle.softmin(x, y, w, h, eps, lam)
     xc, yc = centred(x, y)
-    split = 8 * 3 * 2.0 ** -16 * lam * np.linalg.norm(xc, axis=1) * 2 * np.linalg.norm(yc, axis=1).max()
+    if radius is None:
+        radius = 2 * np.linalg.norm(yc, axis=1).max()
+    split = _split_bound(xc, radius, lam)
     bound = softmin_fp32_bound(x, y, w.astype(np.float64), h.astype(np.float64), eps, lam, ref) + split
     err = np.abs(out - ref)
     assert np.all(np.isfinite(out))
@@ -151,12 +225,12 @@ def test_softmin_bf16_matches_oracle(n, m, d, eps_rel):
 
 
 def test_softmin_bf16_fibres_is_close_to_fp32_accuracy():
-    # clustered fibres: the split error scales with the cluster radius, so the
-    # result is far inside the generic bound
+    # clustered fibres: the split error scales with the cluster radius
     x, a, y, b = synth.fiber_pair(6000, 20, seed=3)
+    x = _inside(x, y)
     rng = np.random.default_rng(9)
     h = (rng.standard_normal(6000)).astype(np.float32)
-    err = _check_bf16(x, y, b, h, 1.0, 1.0, "fibres")
+    err = _check_bf16(x, y, b, h, 1.0, 1.0, "fibres", radius=_offset_radius(y, b))
     assert np.max(err) < 5e-3
 
 
