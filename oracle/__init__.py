@@ -51,6 +51,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = _I
+            lib.oracle_set_num_threads.argtypes = [_I]
+            lib.oracle_set_num_threads.restype = None
             lib.oracle_softmin.argtypes = [_I64, _I64, _I, _P, _P, _P, _P, _D, _D, _P]
             lib.oracle_softmin.restype = None
             lib.oracle_diameter.argtypes = [_I64, _I64, _I, _P, _P]
@@ -117,6 +119,11 @@ def _reach(reach):
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops run on."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on (timing only)."""
+    _load().oracle_set_num_threads(int(k))
 
 
 def softmin(rows, cols, w, h, eps, lam=1.0, p=2.0):

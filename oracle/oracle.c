@@ -60,6 +60,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Sets the number of threads of the OpenMP loops (k >= 1; no effect without
+ * OpenMP).  Used to time the oracle on one core and on all cores. */
+void oracle_set_num_threads(int k) {
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 static int is_balanced(double reach) { return !(reach > 0.0) || isinf(reach); }
 
 /* Cost C(x, y) = |x - y|^p / p (Section 2, the cost function), evaluated from
