@@ -233,14 +233,32 @@ def predict_potentials(net: WarmStartNet, x, a, y, b, blur: float, precision: st
 
 def sinkhorn_divergence_warm(net: WarmStartNet, x, a, y, b, blur: float, scaling: float = 0.9,
                              start_steps=None, net_precision: str = "bf16x3",
-                             n_clusters: int = 0, kmeans_iters: int = 10, **kw):
+                             n_clusters: int = 0, kmeans_iters: int = 10, start: str = "network",
+                             **kw):
     """S_eps(alpha, beta) with the learned warm start: predicted starting values and a
     schedule from start_scale = blur / scaling^start_steps down to blur.  Non-finite
     predictions make the solver run cold (stats["warm_fallback"] = 1).  Returns
-    (S, potentials, stats) like sinkhorn_divergence(..., potentials=True)."""
-    s = net.meta.get("start_steps", 5) if start_steps is None else start_steps
-    init, labels = predict_potentials(net, x, a, y, b, blur, net_precision, n_clusters,
-                                      kmeans_iters, return_labels=True)
+    (S, potentials, stats) like sinkhorn_divergence(..., potentials=True).
+
+    start="zero" is the ablation of the network: the same clustering, the same shortened
+    schedule and the same checked start, but every starting value 0 instead of the
+    prediction (net may be None)."""
+    if start not in ("network", "zero"):
+        raise ValueError("start must be 'network' or 'zero'")
+    if start == "network":
+        s = net.meta.get("start_steps", 5) if start_steps is None else start_steps
+        init, labels = predict_potentials(net, x, a, y, b, blur, net_precision, n_clusters,
+                                          kmeans_iters, return_labels=True)
+    else:
+        if start_steps is None:
+            s = net.meta.get("start_steps", 5) if net is not None else 5
+        else:
+            s = start_steps
+        tk = cluster_tokens(x, a, y, b, n_clusters, kmeans_iters)
+        labels = (tk["labels_x"], tk["labels_y"])
+        zx = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
+        zy = torch.zeros(y.shape[0], dtype=torch.float32, device=y.device)
+        init = (zx, zy, zx.clone(), zy.clone())
     kw.pop("potentials", None)
     # the solver's clustered layout reuses the token clustering (same K-means on the
     # same packed points) instead of running the K-means again
