@@ -171,6 +171,27 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
                 float *out);
 
 /*
+ * skh_softmin for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, same kernels and the same result as skh_softmin, but the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Its workspace is a fixed device array of 64 MiB compiled into the library,
+ * one copy per device, held from the first context on that device until the
+ * process ends.  Roughly (n + m) * 4 * (kp + 4) bytes plus the per-chunk
+ * softmin partials must fit (kp = packed width, 64 for d = 60), e.g. a few
+ * 10^4 points at d = 60; larger problems get SKH_EINVAL with the byte count
+ * before any work is enqueued.  Every call on a device shares that device's
+ * array and leaves its contents behind (nothing in it needs to start at
+ * zero): calls that overlap on one device (two streams, two host threads,
+ * two contexts) race and must be serialised by the caller.  The BF16 split
+ * path synchronises the stream once (the padded column count), as
+ * skh_softmin does.  Errors: as skh_softmin.
+ */
+int skh_softmin_noalloc(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m,
+                        int32_t d, const float *w, const float *h, double eps, double lam,
+                        int32_t precision, float *out);
+
+/*
  * Symmetric, debiased Sinkhorn divergence S_{eps,rho}(alpha, beta), eq. (5),
  * evaluated through its dual form eq. (6) after the averaged symmetric loop
  * with eps-scaling (Algorithm).  Outputs (all nullable):

@@ -79,6 +79,8 @@ SIGNATURES = {
     "skh_workspace_bytes": (_c_i32, [_c_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "skh_softmin": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _c_d, _c_d,
                              _c_i32, _c_vp]),
+    "skh_softmin_noalloc": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp,
+                                     _c_d, _c_d, _c_i32, _c_vp]),
     "skh_sinkhorn_divergence": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32,
                                          ctypes.POINTER(SkhParams), ctypes.POINTER(_c_d), _c_vp,
                                          _c_vp, _c_vp, _c_vp, ctypes.POINTER(SkhStats)]),

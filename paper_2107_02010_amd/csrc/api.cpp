@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,38 @@
 #include "host_util.h"
 
 thread_local std::string g_create_err;
+
+// Device scratch of the allocation-free softmin entry (skh_softmin_noalloc): a fixed
+// array in the code object, so that entry never allocates.  Each device holds its own
+// copy from module load until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: host code uses only the address
+// hipGetSymbolAddress returns on each device (scratch_address), never the name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// The scratch array's address on `device`, looked up once per device (with that
+// device current) and kept for every later context of the device.
+int scratch_address(int device, void **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return SKH_EHIP;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SKH_EHIP;
+        }
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return SKH_OK;
+}
+
+}  // namespace
 
 namespace {
 using namespace skh_host;
@@ -147,6 +180,12 @@ int skh_create(skh_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return SKH_EHIP;
     }
+    if (scratch_address(device, &ctx->scratch) != SKH_OK) {
+        g_create_err = "hipGetSymbolAddress of the device scratch array failed";
+        (void)hipHostFree(ctx->host);
+        delete ctx;
+        return SKH_EHIP;
+    }
     *out = ctx;
     return SKH_OK;
 }
@@ -195,9 +234,36 @@ int skh_workspace_bytes(const skh_ctx *ctx, size_t *out) {
     return SKH_OK;
 }
 
-int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
-                const float *w, const float *h, double eps, double lam, int32_t precision,
-                float *out) {
+}  // extern "C"
+
+namespace {
+
+// Where one call of the softmin entry takes its device workspace: the context's
+// growing workspace (slot by slot), or consecutive pieces of the fixed scratch array
+// (the allocation-free entry, which must not allocate).
+struct SoftminRegions {
+    skh_ctx *ctx;
+    bool fixed;
+    size_t used = 0;
+    int get(int slot, size_t bytes, void **out) {
+        if (!fixed) {
+            const int rc = ensure_ws(ctx, slot, bytes);
+            if (rc) return rc;
+            *out = ctx->ws[slot];
+            return SKH_OK;
+        }
+        const size_t off = (used + 255) & ~size_t(255);
+        if (!ctx->scratch || off + bytes > kScratchBytes)
+            return fail(ctx, SKH_EINVAL, "internal: scratch region out of range");
+        *out = static_cast<char *>(ctx->scratch) + off;
+        used = off + bytes;
+        return SKH_OK;
+    }
+};
+
+int softmin_impl(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
+                 const float *w, const float *h, double eps, double lam, int32_t precision,
+                 float *out, bool no_alloc) {
     if (!ctx) return SKH_EINVAL;
     if (!x || !y || !w || !h || !out) return fail(ctx, SKH_EINVAL, "NULL array argument");
     if (n < 1 || m < 1) return fail(ctx, SKH_EINVAL, "n and m must be >= 1");
@@ -214,13 +280,14 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     hipStream_t s = ctx->stream;
     const int nbx = skh::bbox_blocks(n), nby = skh::bbox_blocks(m);
 
-    // Phase A: bounding box, packing, and (split path) clustering of the columns.
+    // Phase A (bounding box, packing, clustering of the columns on the split path) and
+    // phase B (column offsets, softmin partials) carve their buffers in two passes: the
+    // first, with no base, measures.
     float *Xp, *Yp, *hnx, *hny, *lwy, *plo, *phi, *lohi;
     double *pmass, *mass;
     int *pbad, *bad;
     Clustered cy;
-    for (int pass = 0; pass < 2; ++pass) {
-        Carver c(pass ? ctx->ws[0] : nullptr);
+    auto carve_a = [&](Carver &c) {
         Xp = c.take<float>((size_t)n * kp);
         Yp = c.take<float>((size_t)m * kp);
         hnx = c.take<float>(n);
@@ -234,10 +301,41 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
         mass = c.take<double>(2);
         bad = c.take<int>(4);
         if (split) cy.carve(c, (int)m, kp, 0);
-        if (!pass) {
-            int rc = ensure_ws(ctx, 0, c.off);
-            if (rc) return rc;
-        }
+    };
+    skh::SoftminBatch batch{};
+    batch.n_jobs = 1;
+    batch.d = d;
+    batch.kscale = (float)(kLog2e / eps);
+    batch.job[0].n_rows = (int)n;
+    float *u, *hperm;
+    float2 *part;
+    auto carve_b = [&](Carver &c, int m_cols) {
+        u = c.take<float>(m_cols);
+        hperm = c.take<float>(m_cols);
+        part = c.take<float2>((size_t)batch.job[0].n_chunks * n);
+    };
+    SoftminRegions regions{ctx, no_alloc};
+    Carver ma(nullptr);
+    carve_a(ma);
+    if (no_alloc) {  // the whole call must fit the scratch array: checked before any work
+        const int m_cols_max = split ? cy.n_pad_max : (int)m;
+        batch.job[0].n_cols = m_cols_max;
+        skh::plan_softmin_batch(batch, target_wgs_softmin(ctx, split));
+        Carver mb(nullptr);
+        carve_b(mb, m_cols_max);
+        const size_t need = ((ma.off + 255) & ~size_t(255)) + mb.off;
+        if (need > kScratchBytes)
+            return fail(ctx, SKH_EINVAL,
+                        "skh_softmin_noalloc: this problem needs " + std::to_string(need) +
+                            " bytes of scratch, more than the fixed " +
+                            std::to_string(kScratchBytes) + " bytes");
+    }
+    void *base_a = nullptr;
+    {
+        const int rc = regions.get(0, ma.off, &base_a);
+        if (rc) return rc;
+        Carver c(base_a);
+        carve_a(c);
     }
     SKH_HIP(skh::launch_bbox_partial(x, nullptr, n, d, plo, phi, pmass, pbad, s));
     SKH_HIP(skh::launch_bbox_partial(y, w, m, d, plo + (size_t)nbx * 64, phi + (size_t)nbx * 64,
@@ -261,24 +359,16 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     }
 
     // Phase B: column offsets, the softmin, the merge.
-    skh::SoftminBatch batch{};
-    batch.n_jobs = 1;
-    batch.d = d;
-    batch.kscale = (float)(kLog2e / eps);
-    batch.job[0].n_rows = (int)n;
     batch.job[0].n_cols = m_cols;
     const int wgs = skh::plan_softmin_batch(batch, target_wgs_softmin(ctx, split));
-    float *u, *hperm;
-    float2 *part;
-    for (int pass = 0; pass < 2; ++pass) {
-        Carver c(pass ? ctx->ws[1] : nullptr);
-        u = c.take<float>(m_cols);
-        hperm = c.take<float>(m_cols);
-        part = c.take<float2>((size_t)batch.job[0].n_chunks * n);
-        if (!pass) {
-            int rc = ensure_ws(ctx, 1, c.off);
-            if (rc) return rc;
-        }
+    {
+        Carver mb(nullptr);
+        carve_b(mb, m_cols);
+        void *base_b = nullptr;
+        const int rc = regions.get(1, mb.off, &base_b);
+        if (rc) return rc;
+        Carver c(base_b);
+        carve_b(c, m_cols);
     }
     if (split) {
         SKH_HIP(skh::launch_permute(h, cy.perm_pad, cy.n_pad, hperm, s));
@@ -302,6 +392,22 @@ int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t
     }
     SKH_HIP(skh::launch_softmin_finish(part, J.n_chunks, n, hnx, eps, lam, out, s));
     return SKH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int skh_softmin(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m, int32_t d,
+                const float *w, const float *h, double eps, double lam, int32_t precision,
+                float *out) {
+    return softmin_impl(ctx, x, n, y, m, d, w, h, eps, lam, precision, out, false);
+}
+
+int skh_softmin_noalloc(skh_ctx *ctx, const float *x, int64_t n, const float *y, int64_t m,
+                        int32_t d, const float *w, const float *h, double eps, double lam,
+                        int32_t precision, float *out) {
+    return softmin_impl(ctx, x, n, y, m, d, w, h, eps, lam, precision, out, true);
 }
 
 // Independent problems solved together (block-diagonal softmins): pair k owns the

@@ -19,6 +19,7 @@ struct skh_ctx {
     size_t ws_bytes[4] = {0, 0, 0, 0};
     size_t ws_limit = 0;   // cap on the sum of ws_bytes (0: none)
     void *host = nullptr;  // pinned, kHostBytes
+    void *scratch = nullptr;  // this device's address of the fixed scratch array (api.cpp)
     int num_cus = 256;
     std::vector<hipEvent_t> events;  // pairs bracketing timed softmin launches
     std::string err;
