@@ -248,19 +248,56 @@ def grad_x(x, a, y, b, f, g, p, eps):
     return out
 
 
+def grad_x_p(x, a, y, b, f, g, p, blur, cost_p=2.0):
+    """Gradient of S with respect to x for the cost |x - y|^P / P (Section 2), from the
+    dual vectors at eps = blur^P: the envelope theorem on eq. (3) for the two OT terms of
+    eq. (5) that depend on x,
+
+      grad_i = sum_j pi_ij |x_i - y_j|^{P-2} (x_i - y_j) - sum_k pi^aa_ik |x_i - x_k|^{P-2} (x_i - x_k),
+
+    pi from eq. (4) with that cost (the self term carries the factor 2 of a plan whose
+    two marginals both move with x, times the 1/2 of eq. (5)).  A pair at distance 0
+    contributes 0 (its difference vanishes; for P = 1 this is the zero subgradient).
+    Dense numpy in FP64."""
+    P = float(cost_p)
+    eps = float(blur) ** P
+    x, y = _pts(x), _pts(y)
+    a, b, f, g, p = (_f64(v) for v in (a, b, f, g, p))
+
+    def term(X, A, Y, B, F, G):
+        diff = X[:, None, :] - Y[None, :, :]
+        D = np.sqrt((diff ** 2).sum(-1))
+        C = D ** P / P
+        pi = A[:, None] * B[None, :] * np.exp((F[:, None] + G[None, :] - C) / eps)
+        with np.errstate(divide="ignore"):
+            w = np.where(D > 0.0, D ** (P - 2.0), 0.0)
+        return ((pi * w)[:, :, None] * diff).sum(1)
+
+    return term(x, a, y, b, f, g) - term(x, a, x, a, p, p)
+
+
 def grad_y(x, a, y, b, f, g, q, eps):
     """Gradient of S with respect to y: the x formula with the roles of the two
     measures exchanged (S is symmetric in (alpha, beta))."""
     return grad_x(y, b, x, a, g, f, q, eps)
 
 
-def grad_weights(f, p, blur, reach=None):
+def grad_weights(f, p, blur, reach=None, cost_p=2.0):
     """dS/d alpha_i from (f, p) (dS/d beta_j from (g, q)): (rho + eps)(e^{-p/rho} - e^{-f/rho}),
-    f - p when balanced (envelope theorem on the dual of eq. (3), Section 2)."""
+    f - p when balanced (envelope theorem on the dual of eq. (3), Section 2); for the cost
+    |x - y|^P / P the same expression at eps = blur^P, rho = reach^P."""
     f, p = _f64(f), _f64(p)
     out = np.empty_like(f)
-    _load().oracle_grad_weights(f.size, _ptr(f), _ptr(p), float(blur), _reach(reach), _ptr(out))
-    return out
+    P = float(cost_p)
+    if P == 2.0:
+        _load().oracle_grad_weights(f.size, _ptr(f), _ptr(p), float(blur), _reach(reach),
+                                    _ptr(out))
+        return out
+    eps = float(blur) ** P
+    if reach is None or not np.isfinite(reach):
+        return f - p
+    rho = float(reach) ** P
+    return -(rho + eps) * np.exp(-p / rho) * np.expm1(-(f - p) / rho)
 
 
 def flip_fibers(x, points):
@@ -307,22 +344,48 @@ def sinkhorn_divergence(x, a, y, b, blur, reach=None, scaling=0.9, diam=None, ex
 
 
 def barycenter_steps(x, a, maps, steps, blur, reach=None, scaling=0.9, lr=1.0, extra_iters=0,
-                     diam=None):
+                     diam=None, start_scale=0.0):
     """Gradient descent on the support of alpha for (1/K) sum_k S(alpha, beta_k)
     (Section 3, track density atlas): x <- x - lr * mean_k grad_x S(alpha, beta_k) / a,
     each S and gradient from the loop's dual vectors (full solve per map; diam: the
-    largest scale of every solve, None: each pair's own).  Returns (x, mean S per step)."""
+    largest scale of every solve, None: each pair's own).  Returns (x, mean S per step).
+
+    start_scale > 0: every step after the first starts from the previous step's dual
+    vectors with the scale list [start_scale, start_scale * scaling, ..., blur]: the self
+    vector p of alpha from the alpha<->alpha loop alone (a run of the loop on the pair
+    (alpha, alpha) started from (p, p, p, p), whose p is that loop), the cross vectors
+    f_k, g_k from a run on (alpha, beta_k) started from (f_k, g_k, p, q_k) (the cross loop
+    reads neither p nor q_k), and q_k held at its value from the first step (beta_k does
+    not move)."""
     x = _pts(x).copy()
     a = _f64(a)
+    eps = float(blur) ** 2
     hist = []
+    prev = None
     for _ in range(steps):
         grad = np.zeros_like(x)
         tot = 0.0
-        for y, b in maps:
-            S, r = sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling, diam=diam,
-                                       extra_iters=extra_iters)
-            grad += grad_x(x, a, y, b, r["f"], r["g"], r["p"], float(blur) ** 2)
+        warm = start_scale > 0.0 and prev is not None
+        if warm:
+            p_prev, fs, gs, qs = prev
+            p = sinkhorn(x, a, x, a, blur, reach, scaling, diam=start_scale,
+                         extra_iters=extra_iters, init=(p_prev, p_prev, p_prev, p_prev))["p"]
+        cur_f, cur_g, cur_q = [], [], []
+        for k, (y, b) in enumerate(maps):
+            if warm:
+                r = sinkhorn(x, a, y, b, blur, reach, scaling, diam=start_scale,
+                             extra_iters=extra_iters, init=(fs[k], gs[k], p, qs[k]))
+                r["p"], r["q"] = p, qs[k]
+                S = divergence(a, b, r["f"], r["g"], p, qs[k], blur, reach)
+            else:
+                S, r = sinkhorn_divergence(x, a, y, b, blur, reach, scaling=scaling, diam=diam,
+                                           extra_iters=extra_iters)
+            grad += grad_x(x, a, y, b, r["f"], r["g"], r["p"], eps)
             tot += S
+            cur_f.append(r["f"])
+            cur_g.append(r["g"])
+            cur_q.append(r["q"])
+        prev = (r["p"], cur_f, cur_g, cur_q)
         x = x - lr * (grad / len(maps)) / a[:, None]
         hist.append(tot / len(maps))
     return x, hist

@@ -722,3 +722,72 @@ def test_label_transfer_flip_copies_carry_the_fibre_weight():
     assert r1["converged"] and r2["converged"]
     np.testing.assert_allclose(lab_f, 2 * lab_2, rtol=1e-8, atol=1e-12)
     np.testing.assert_allclose(score_f, 2 * score_2, rtol=1e-8)
+
+
+# ------------------------------------------------ gradients, cost exponent p --
+
+def _conv_p(x, a, y, b, blur, reach, cost_p, tol=1e-14):
+    S, r = oracle.sinkhorn_divergence(x, a, y, b, blur, reach, scaling=0.5, tol=tol,
+                                      max_iters=50000, check_every=1, p=cost_p)
+    assert r["converged"], r["marginal_err"]
+    return S, r
+
+
+@pytest.mark.parametrize("cost_p,reach", [(1.5, None), (1.5, 0.7), (1.0, None), (1.0, 0.7),
+                                          (1.25, 0.9)])
+def test_gradient_p_finite_differences(cost_p, reach):
+    # grad_x S for |x - y|^p / p (eps = blur^p) against central differences of the
+    # oracle's converged S; the self term's zero-distance pairs do not move with x
+    rng = np.random.default_rng(61)
+    x, y = rng.uniform(size=(5, 2)), rng.uniform(size=(6, 2))
+    a, b = _u(5), _w(6, 62)
+    blur = 0.3
+    S, r = _conv_p(x, a, y, b, blur, reach, cost_p)
+    G = oracle.grad_x_p(x, a, y, b, r["f"], r["g"], r["p"], blur, cost_p)
+    h = 1e-5
+    fd = np.zeros_like(x)
+    for i in range(5):
+        for k in range(2):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd[i, k] = (_conv_p(xp, a, y, b, blur, reach, cost_p)[0]
+                        - _conv_p(xm, a, y, b, blur, reach, cost_p)[0]) / (2 * h)
+    np.testing.assert_allclose(G, fd, rtol=2e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("cost_p", [1.5, 1.0])
+def test_weight_gradient_p_finite_differences(cost_p):
+    rng = np.random.default_rng(63)
+    x, y = rng.uniform(size=(4, 2)), rng.uniform(size=(5, 2))
+    a, b = _w(4, 64), _w(5, 65, total=1.2)
+    blur, reach = 0.3, 0.8
+    S, r = _conv_p(x, a, y, b, blur, reach, cost_p)
+    Ga = oracle.grad_weights(r["f"], r["p"], blur, reach, cost_p=cost_p)
+    h = 1e-6
+    for i in range(4):
+        ap, am = a.copy(), a.copy()
+        ap[i] += h
+        am[i] -= h
+        fd = (_conv_p(x, ap, y, b, blur, reach, cost_p)[0]
+              - _conv_p(x, am, y, b, blur, reach, cost_p)[0]) / (2 * h)
+        assert fd == pytest.approx(Ga[i], rel=1e-6, abs=1e-10)
+
+
+def test_gradient_p_reduces_to_p2_and_dirac():
+    # p = 2: the same numbers as the p = 2 gradient (a separate implementation, in C)
+    rng = np.random.default_rng(66)
+    x, y = rng.uniform(size=(6, 3)), rng.uniform(size=(7, 3))
+    a, b = _u(6), _w(7, 67)
+    S, r = _conv(x, a, y, b, 0.25, 0.9)
+    np.testing.assert_allclose(oracle.grad_x_p(x, a, y, b, r["f"], r["g"], r["p"], 0.25, 2.0),
+                               oracle.grad_x(x, a, y, b, r["f"], r["g"], r["p"], 0.0625),
+                               rtol=1e-12, atol=1e-15)
+    # one balanced Dirac each: the plan moves the unit mass, grad = |x - y|^{p-2} (x - y)
+    x1, y1 = np.array([[0.2, 0.1]]), np.array([[-0.3, 0.5]])
+    for P in (1.0, 1.5):
+        S, r = _conv_p(x1, [1.0], y1, [1.0], 0.3, None, P)
+        D = float(np.linalg.norm(x1 - y1))
+        np.testing.assert_allclose(oracle.grad_x_p(x1, [1.0], y1, [1.0], r["f"], r["g"], r["p"],
+                                                   0.3, P), D ** (P - 2.0) * (x1 - y1),
+                                   rtol=1e-10)

@@ -147,3 +147,35 @@ def test_barycenter_two_steps_geometric_approach():
     S0 = 0.5 * float(np.sum((x0 - y) ** 2))
     assert hist[0] == pytest.approx(S0, rel=1e-12)
     assert hist[1] == pytest.approx(S0 / 4.0, rel=1e-12)
+
+
+def test_barycenter_warm_steps_on_dirac_maps_stay_geometric():
+    # A warm start changes where each step's loops begin, not what the Dirac gradient is:
+    # the distance to y still halves at every step with lr = 1/2.
+    x0 = np.array([[1.0, 2.0]])
+    y = np.array([[-1.0, 0.0]])
+    x3, hist = oracle.barycenter_steps(x0, np.array([1.0]), [(y, np.array([1.0]))], 3,
+                                       blur=0.2, lr=0.5, scaling=0.5, start_scale=0.4)
+    np.testing.assert_allclose(x3, y + 0.125 * (x0 - y), rtol=0, atol=1e-12)
+    S0 = 0.5 * float(np.sum((x0 - y) ** 2))
+    np.testing.assert_allclose(hist, [S0, S0 / 4.0, S0 / 16.0], rtol=1e-12)
+
+
+def test_barycenter_warm_steps_reach_the_cold_fixed_points():
+    # With enough iterations at blur every step's loops converge, so the warm-started
+    # descent (loops started from the previous step's vectors, q_k held) takes the same
+    # steps as the cold one.  S differs only by the balanced gauge of (f, g), which the
+    # warm start inherits: c * (sum a - sum b), with the FP32 weights' sums off 1 by ~1e-8.
+    import synth
+    maps = synth.density_maps(2, seed=1, grid=12, n_tubes=2, nonzero=(60, 90),
+                              sigma=(1.0, 1.5), jitter=1.0)
+    x0, a = synth.barycenter_support(maps, 40, seed=2)
+    kw = dict(blur=1.0, scaling=0.7, extra_iters=1000, diam=20.0)
+    xc, hc = oracle.barycenter_steps(x0, a, maps, 2, **kw)
+    xw, hw = oracle.barycenter_steps(x0, a, maps, 2, start_scale=3.0, **kw)
+    np.testing.assert_allclose(xw, xc, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(hw, hc, rtol=1e-8)
+    # the warm start matters on the Algorithm's schedule alone (one iteration per scale)
+    xs, _ = oracle.barycenter_steps(x0, a, maps, 2, start_scale=3.0,
+                                    **dict(kw, extra_iters=0))
+    assert np.abs(xs - xc).max() > 1e-3
