@@ -452,6 +452,23 @@ def bench_barycenter(args, skh, synth):
         dt, (x1, S, _) = _timed(lambda: B.step(X), args.steps, args.warmup)
         res[leg] = {"s_per_step": round(dt, 4), "mean_S": S}
         print(f"[bench] barycenter step ({leg}): {dt:.3f} s", file=sys.stderr, flush=True)
+    # a 10-step descent, every step after the first started from the previous step's
+    # vectors with the scale list [3, 3 q, ..., blur] (batched cross loops)
+    B = Barycenter(A, ym, blur=1.0, scaling=0.9, x0=X, batched=True, start_scale=3.0)
+    B._setup(X)
+    x, hist, times = X, [], []
+    for k in range(10):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, S, _ = B.step(x)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        hist.append(S)
+        print(f"[bench] warm-started descent step {k + 1}/10: S={S:.8g} {times[-1]:.3f} s",
+              file=sys.stderr, flush=True)
+    res["descent_warm"] = {"start_scale": 3.0, "s_first_step": round(times[0], 4),
+                           "s_per_warm_step": round(sum(times[1:]) / 9, 4),
+                           "s_total_10_steps": round(sum(times), 4), "S_history": hist}
     m_total = sum(len(c) for c, _ in maps)
     out = {"metric": "time per barycenter step, 10 density maps (128^3), 200k support points",
            "value": res["batched"]["s_per_step"], "unit": "s", "n_gpus": 1,
@@ -465,6 +482,7 @@ def bench_barycenter(args, skh, synth):
                                   "of all maps, 10 gradients"},
            "batched": res["batched"], "per_map": res["per_map"],
            "per_map_multiscale": res["per_map_multiscale"],
+           "descent_warm": res["descent_warm"],
            "speedup_batched": round(res["per_map"]["s_per_step"] / res["batched"]["s_per_step"], 3),
            "S_rel_diff_multiscale": abs(res["per_map_multiscale"]["mean_S"] - res["batched"]["mean_S"])
                                     / abs(res["batched"]["mean_S"])}

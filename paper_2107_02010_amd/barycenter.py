@@ -21,6 +21,14 @@ over all maps (row tiles of each map's copy of the support against that map's
 columns only).  With multiscale=True each map's cross loop runs the coarse-to-fine
 scheme of Section 2 instead (K-means coarse loop, jump, cluster-block truncation at
 e^{-trunc_theta}), from a cold start with p and q_k fixed; the self vectors stay dense.
+
+Warm start (start_scale > 0): the first step runs the whole scale list from the
+common largest scale; every later step starts the self loop of alpha and the K
+cross loops from the previous step's vectors (p, f_k, g_k) with a scale list that
+begins at start_scale (start_scale, start_scale * scaling, ..., blur), while the
+q_k stay those of the first step.  The support moves a little per step, so the
+previous vectors are close to the new ones and the long descent of sigma from the
+diameter is not repeated.
 """
 from __future__ import annotations
 
@@ -36,7 +44,8 @@ class Barycenter:
     def __init__(self, a, maps, blur: float = 1.0, reach=None, scaling: float = 0.9,
                  lr: float = 1.0, precision: str = "fp32", extra_iters: int = 0, x0=None,
                  batched: bool = True, multiscale: bool = False, trunc_theta: float = 20.0,
-                 n_clusters: int = 0, tol: float = 0.0, max_iters: int = 1000):
+                 n_clusters: int = 0, tol: float = 0.0, max_iters: int = 1000,
+                 start_scale: float = 0.0):
         self.a = a
         self.maps = maps
         self.multiscale = multiscale
@@ -48,6 +57,11 @@ class Barycenter:
         self.lr = lr
         self.d = None if x0 is None else max(diameter(x0, y) for y, _ in maps)
         self.q = None
+        # warm start: largest scale of every step after the first (0: each step cold)
+        self.start_scale = float(start_scale)
+        if self.start_scale > 0.0 and multiscale:
+            raise ValueError("the warm-started descent runs the dense cross loops")
+        self.prev = None  # (p, [f_k], [g_k]) of the last step
 
     def _setup(self, x):
         if self.d is None:
@@ -58,36 +72,49 @@ class Barycenter:
     def step(self, x):
         """One descent step; returns (new x, mean S, per-map potential dicts)."""
         self._setup(x)
-        p, _ = self_potential(x, self.a, diameter=self.d, **self.kw)
+        warm = self.start_scale > 0.0 and self.prev is not None
+        if warm:
+            p, _ = self_potential(x, self.a, init=self.prev[0], start_scale=self.start_scale,
+                                  **self.kw)
+        else:
+            p, _ = self_potential(x, self.a, diameter=self.d, **self.kw)
+        top = self.start_scale if warm else self.d
         grad = torch.zeros_like(x)
         total = 0.0
         pots = []
         if self.batched:
             K, n = len(self.maps), x.shape[0]
             m = sum(y.shape[0] for y, _ in self.maps)
-            init = (torch.zeros(K * n, dtype=torch.float32, device=x.device),
-                    torch.zeros(m, dtype=torch.float32, device=x.device), p.repeat(K),
-                    torch.cat(self.q))
+            if warm:
+                f0, g0 = torch.cat(self.prev[1]), torch.cat(self.prev[2])
+            else:
+                f0 = torch.zeros(K * n, dtype=torch.float32, device=x.device)
+                g0 = torch.zeros(m, dtype=torch.float32, device=x.device)
+            init = (f0, g0, p.repeat(K), torch.cat(self.q))
             kw = {k: v for k, v in self.kw.items() if k != "precision"}
             S, pot, _ = sinkhorn_divergence_batched(
                 [x] * K, [self.a] * K, [y for y, _ in self.maps], [b for _, b in self.maps],
-                diameter=self.d, init=init, fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True, **kw)
+                diameter=top, init=init, fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True, **kw)
             for k, (y, b) in enumerate(self.maps):
                 pk = dict(f=pot["f"][k], g=pot["g"][k], p=pot["p"][k], q=pot["q"][k])
                 grad += grad_x(x, self.a, y, b, pk["f"], pk["g"], pk["p"], self.kw["blur"])
                 pots.append(pk)
             grad /= K
+            self.prev = (p, [u["f"] for u in pots], [u["g"] for u in pots])
             return x - self.lr * grad / self.a[:, None], sum(S) / K, pots
-        for (y, b), q in zip(self.maps, self.q):
+        for k, ((y, b), q) in enumerate(zip(self.maps, self.q)):
             if self.multiscale:  # cold cross loop (coarse phase first), p and q fixed
                 S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d,
                                                 init=(None, None, p, q),
                                                 fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
                                                 **self.kw, **self.ms_kw)
             else:
-                zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
-                zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
-                S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=self.d,
+                if warm:
+                    zf, zg = self.prev[1][k], self.prev[2][k]
+                else:
+                    zf = torch.zeros(x.shape[0], dtype=torch.float32, device=x.device)
+                    zg = torch.zeros(y.shape[0], dtype=torch.float32, device=x.device)
+                S, pot, _ = sinkhorn_divergence(x, self.a, y, b, diameter=top,
                                                 init=(zf, zg, p, q),
                                                 fixed=SKH_FIX_P | SKH_FIX_Q, potentials=True,
                                                 **self.kw)
@@ -95,6 +122,7 @@ class Barycenter:
             total += S
             pots.append(pot)
         grad /= len(self.maps)
+        self.prev = (p, [u["f"] for u in pots], [u["g"] for u in pots])
         return x - self.lr * grad / self.a[:, None], total / len(self.maps), pots
 
 
@@ -115,7 +143,8 @@ def barycenter_step(x, a, maps, blur: float = 1.0, reach=None, scaling: float = 
 
 
 def wasserstein_barycenter(x0, a, maps, steps: int = 10, **kw):
-    """Runs `steps` gradient steps from x0; returns (x, list of mean S per step)."""
+    """Runs `steps` gradient steps from x0; returns (x, list of mean S per step).
+    start_scale > 0 warm-starts every step after the first (see Barycenter)."""
     B = Barycenter(a, maps, x0=x0, **kw)
     x = x0.clone()
     history = []

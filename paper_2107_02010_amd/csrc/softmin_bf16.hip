@@ -11,6 +11,9 @@
 //                   row and cluster)   FP32 accumulate, error ~ 3 * 2^-16 |x| |dy|)
 //
 // so the split error scales with the cluster radius |dy|, not with |y|.
+// The shift re-reads the row k * x_i from memory at each cluster change (the
+// register file holds only its bf16 split), which keeps the kernel at four
+// workgroups per CU.
 //
 // Three more coordinates ride along in the contraction, so that the matrix
 // cores deliver the exponent itself:
@@ -30,9 +33,11 @@
 // (first mass, overflow): then the larger of the block's maximum and the sum
 // so far sets the new level and the block is re-summed from the accumulators.
 // A row that holds mass keeps a sum >= 2^-4 (sums only grow; a cluster change
-// re-rounds the level by far less), so once every row of a wave holds mass the per-half
-// overflow test runs, and a block whose terms all lie below 2^T of the level
-// (T = B.skip_log2: -48, lower for column sets beyond 2^20 points) is skipped
+// re-rounds the level by far less), so once every row of a wave holds mass the
+// overflow test runs only for blocks with a term above 2^40 (smaller terms cannot
+// carry a sum to FP32 overflow over at most 2^23 blocks), and a block whose terms
+// all lie below 2^T of the level (T = B.skip_log2: -48, lower for column sets
+// beyond 2^20 points) is skipped
 // after its products (it cannot move any row sum beyond rounding); the products
 // of every pair are still computed.
 //
@@ -59,20 +64,22 @@ static __device__ __forceinline__ float xor32_max(float v) {
     return fmaxf(__uint_as_float(t[0]), __uint_as_float(t[1]));
 }
 
+// 64-column tiles and at most 128 registers per lane: four workgroups per CU.
 template <int KP>
-__global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
+__global__ __launch_bounds__(256, 4) void k_softmin_bf16(const SoftminBatch B) {
+    constexpr int TC = 64;  // columns staged per tile (a divisor of kColsPerTile)
     constexpr int H = KP / 2;        // dims per lane half
     constexpr int S = H / 8;         // k-steps of 16 (8 bf16 per lane)
     constexpr int RSB = KP * 2 + 16; // LDS row stride in bytes (padding against bank conflicts)
     constexpr int V16 = KP / 8;      // 16-byte chunks per packed column plane
-    constexpr int NCH = kColsPerTile * V16 / 256;  // chunks per thread per plane and tile
-    constexpr int NBT = kColsPerTile / 32;         // 32-column blocks per tile
+    constexpr int NCH = (TC * V16 + 255) / 256;  // chunks per thread per plane and tile
+    constexpr int NBT = TC / 32;                 // 32-column blocks per tile
     constexpr int NCE = NBT * KP;                  // centroid floats per tile
     constexpr int NCP = (NCE + 255) / 256;           // centroid floats per thread
-    __shared__ __attribute__((aligned(16))) unsigned char lhi[kColsPerTile * RSB];
-    __shared__ __attribute__((aligned(16))) unsigned char llo[kColsPerTile * RSB];
+    __shared__ __attribute__((aligned(16))) unsigned char lhi[TC * RSB];
+    __shared__ __attribute__((aligned(16))) unsigned char llo[TC * RSB];
     __shared__ float lcent[NBT][KP];
-    __shared__ int lcl[NBT];
+    __shared__ __attribute__((aligned(8))) int lcl[NBT];
 
     const int wg = blockIdx.x;
     int q = 0;
@@ -120,26 +127,21 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     const int ic = i < re ? i : re - 1;
     const bool wave_active = rb + wave * 32 < re;
 
-    // Row: k * x_i in FP32 (for the cluster shift) and its bf16 hi/lo split.
-    float xf[H];
-    {
-        const float *rp = rows + (size_t)ic * KP + h * H;
-#pragma unroll
-        for (int s = 0; s < H; s += 4) {
-            const float4 v = *reinterpret_cast<const float4 *>(rp + s);
-            xf[s] = v.x * kscale;
-            xf[s + 1] = v.y * kscale;
-            xf[s + 2] = v.z * kscale;
-            xf[s + 3] = v.w * kscale;
-        }
-    }
+    // Row: k * x_i split into bf16 hi/lo in registers.  The FP32 row that the cluster
+    // shift needs is read again from memory (L2) at each cluster change rather than held
+    // in 32 more registers.
+    const float *rowp = rows + (size_t)ic * KP + h * H;
     bf16x8 xh[S], xl[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+        const float4 v0 = *reinterpret_cast<const float4 *>(rowp + s * 8);
+        const float4 v1 = *reinterpret_cast<const float4 *>(rowp + s * 8 + 4);
+        const float xs[8] = {v0.x * kscale, v0.y * kscale, v0.z * kscale, v0.w * kscale,
+                             v1.x * kscale, v1.y * kscale, v1.z * kscale, v1.w * kscale};
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int dim = h * H + s * 8 + e;
-            const float v = xf[s * 8 + e];
+            const float v = xs[e];
             const __bf16 hi = static_cast<__bf16>(v);
             const __bf16 lo = static_cast<__bf16>(v - static_cast<float>(hi));
             const bool aug = dim >= d && dim < d + 3;
@@ -173,8 +175,8 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
     float pfc[NCP];
     int pfk = -1;
     auto next_tile = [&](int &r, int &a, int &e) -> bool {
-        if (r >= 0 && a + kColsPerTile < e) {
-            a += kColsPerTile;
+        if (r >= 0 && a + TC < e) {
+            a += TC;
             return true;
         }
         for (r = r < 0 ? r0 : r + rstep; r < nranges; r += rstep) {
@@ -187,26 +189,35 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
         }
         return false;
     };
-    auto prefetch = [&](int a, int e) {
+    // Tile loads go through buffer descriptors based at the tile (scalar registers) with
+    // 32-bit lane offsets; reads past the end of the column planes return zeros.  Columns
+    // of a tile past its range end are staged but never used (ranges end on 32-column
+    // blocks and only the blocks inside the range are computed).
+    auto prefetch = [&](int a_, int e_) {
+        const int a = __builtin_amdgcn_readfirstlane(a_);
+        const int e = __builtin_amdgcn_readfirstlane(e_);
+        const long long rem = (long long)(n_cols - a) * (KP * 2);
+        const int nrec = rem > 0x7fffffff ? 0x7fffffff : (int)rem;
+        const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char *>(chi) + (size_t)a * (KP * 2), (short)0, nrec, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char *>(clo) + (size_t)a * (KP * 2), (short)0, nrec, 0x00020000);
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
-            const int idx = tid + 256 * k;
-            const int c = idx / V16, v = idx - c * V16;
-            const int j = a + c;
-            pfh[k] = make_uint4(0u, 0u, 0u, 0u);
-            pfl[k] = make_uint4(0u, 0u, 0u, 0u);
-            if (j < e) {
-                pfh[k] = *reinterpret_cast<const uint4 *>(chi + ((size_t)j * KP + v * 8) * 2);
-                pfl[k] = *reinterpret_cast<const uint4 *>(clo + ((size_t)j * KP + v * 8) * 2);
+            const unsigned off = (unsigned)(tid + 256 * k) * 16u;
+            if (TC * V16 % 256 == 0 || tid + 256 * k < TC * V16) {
+                pfh[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rh, off, 0, 0));
+                pfl[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rl, off, 0, 0));
             }
         }
+        const int lim = e - a;
+        const float *tc = blk_cent + (size_t)(a >> 5) * KP;
 #pragma unroll
         for (int c = 0; c < NCP; ++c) {
             const int q = tid + 256 * c;
-            const int t = q / KP;
-            pfc[c] = q < NCE && a + 32 * t < e ? blk_cent[(size_t)((a >> 5) + t) * KP + (q - t * KP)] : 0.0f;
+            pfc[c] = q < NCE && 32 * (q / KP) < lim ? tc[(unsigned)q] : 0.0f;
         }
-        if (tid < NBT) pfk = a + 32 * tid < e ? blk_cluster[(a >> 5) + tid] : -1;
+        if (tid < NBT) pfk = 32 * tid < lim ? blk_cluster[(a >> 5) + tid] : -1;
     };
 
     int ri = -1, j0 = 0, jend = 0;
@@ -218,6 +229,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
         for (int k = 0; k < NCH; ++k) {
             const int idx = tid + 256 * k;
             const int c = idx / V16, v = idx - c * V16;
+            if (TC * V16 % 256 != 0 && idx >= TC * V16) break;
             *reinterpret_cast<uint4 *>(lhi + c * RSB + v * 16) = pfh[k];
             *reinterpret_cast<uint4 *>(llo + c * RSB + v * 16) = pfl[k];
         }
@@ -233,13 +245,23 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
         __syncthreads();
 
         const int nblk = wave_active ? min(NBT, (cend - cj0 + 31) >> 5) : 0;
+        static_assert(NBT == 2, "one int2 of cluster ids per tile");
+        const int2 c2 = *reinterpret_cast<const int2 *>(lcl);
+        const int cl0 = __builtin_amdgcn_readfirstlane(c2.x);
+        const int cl1 = __builtin_amdgcn_readfirstlane(c2.y);
         for (int jb = 0; jb < nblk; ++jb) {
-            const int cl = __builtin_amdgcn_readfirstlane(lcl[jb]);
+            const int cl = jb == 0 ? cl0 : cl1;
             if (cl != cur_cluster) {  // wave-uniform: new cluster shift, same reference level
                 cur_cluster = cl;
                 float r = 0.0f;
 #pragma unroll
-                for (int t = 0; t < H; ++t) r = fmaf(xf[t], lcent[jb][h * H + t], r);
+                for (int t = 0; t < H; t += 4) {
+                    const float4 xv = *reinterpret_cast<const float4 *>(rowp + t);
+                    r = fmaf(xv.x * kscale, lcent[jb][h * H + t], r);
+                    r = fmaf(xv.y * kscale, lcent[jb][h * H + t + 1], r);
+                    r = fmaf(xv.z * kscale, lcent[jb][h * H + t + 2], r);
+                    r = fmaf(xv.w * kscale, lcent[jb][h * H + t + 3], r);
+                }
                 shift = xor32_sum(r);
                 const float Rn = set_ref(shift - R);
                 Sl = Sl > 0.0f ? Sl * fast_exp2(R - Rn) : 0.0f;
@@ -249,23 +271,37 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             const unsigned char *ph = lhi + (jb * 32 + li) * RSB + h * H * 2;
             const unsigned char *pl = llo + (jb * 32 + li) * RSB + h * H * 2;
+            // operand reads one k-step ahead of the products; the scheduling fences keep
+            // the compiler from hoisting every read of the block (register pressure)
+            bf16x8 ah = *reinterpret_cast<const bf16x8 *>(ph);
+            bf16x8 al = *reinterpret_cast<const bf16x8 *>(pl);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(ph + s * 16);
-                const bf16x8 al = *reinterpret_cast<const bf16x8 *>(pl + s * 16);
+                bf16x8 nh = ah, nl = al;
+                if (s + 1 < S) {
+                    nh = *reinterpret_cast<const bf16x8 *>(ph + (s + 1) * 16);
+                    nl = *reinterpret_cast<const bf16x8 *>(pl + (s + 1) * 16);
+                }
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh[s], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh[s], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[s], acc, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                ah = nh;
+                al = nl;
             }
             // acc[r] = s_ij - R.  Once every row of the wave holds mass (its sum is
             // >= 2^-4 relative to R), a block whose terms are all below 2^skip_log2
             // cannot change any row sum beyond FP32 rounding: its exponentials are
             // skipped (wave-uniform test on the block maximum).
+            bool big = true;
             if (all_mass) {
                 float mx = acc[0];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
                 if (!__any(mx > B.skip_log2)) continue;
+                // terms <= 2^40 cannot overflow a sum that holds mass (at most 2^23 blocks
+                // per row add 2^44 each): the overflow test runs only for larger terms
+                big = __any(mx > 40.0f);
             }
             // pairwise sum keeps the add chain short
             float ex[16];
@@ -276,7 +312,7 @@ __global__ __launch_bounds__(256, 3) void k_softmin_bf16(const SoftminBatch B) {
 #pragma unroll
                 for (int r = 0; r < w; ++r) ex[r] += ex[r + w];
             float Sn = Sl + ex[0];
-            if (__any(!(Sn < 0x1p59f) || !mass)) {  // wave-uniform: look at whole rows
+            if (big && __any(!(Sn < 0x1p59f) || !mass)) {  // wave-uniform: look at whole rows
             const float Sc = xor32_sum(Sn);
             const bool need = !(Sc < 0x1p59f) || !(Sc >= 0x1p-4f);
             if (__any(need)) {  // wave-uniform: re-level the rows that need it

@@ -35,6 +35,30 @@ def test_barycenter_steps_match_oracle():
     assert torch.isfinite(xg).all()
 
 
+@pytest.mark.parametrize("batched", [True, False])
+def test_barycenter_warm_steps_match_oracle(batched):
+    # every step after the first starts its loops from the previous step's vectors with
+    # the scale list [3, 3 q, ..., blur]; the oracle takes the same warm-started steps
+    from paper_2107_02010_amd.barycenter import wasserstein_barycenter
+    maps = synth.density_maps(3, seed=1, grid=24, n_tubes=3, nonzero=(500, 900),
+                              sigma=(1.0, 2.0), jitter=1.5)
+    x0, a = synth.barycenter_support(maps, 400, seed=2)
+    kw = dict(blur=1.0, reach=None, scaling=0.7, lr=1.0)
+    note(f"warm-started barycenter 3 maps 24^3, 400 support, 3 steps, batched={batched}")
+    xg, hg = wasserstein_barycenter(cuda(x0), cuda(a), [(cuda(c), cuda(w)) for c, w in maps],
+                                    steps=3, start_scale=3.0, batched=batched, **kw)
+    diam = max(np.linalg.norm(np.maximum(x0.max(0), c.max(0)).astype(np.float64)
+                              - np.minimum(x0.min(0), c.min(0)).astype(np.float64))
+               for c, _ in maps)
+    xr, hr = oracle.barycenter_steps(x0, a, maps, 3, diam=diam, start_scale=3.0, **kw)
+    print("S history GPU", hg, "oracle", hr)
+    assert hg[0] == pytest.approx(hr[0], rel=1e-4)
+    assert hg[1] == pytest.approx(hr[1], rel=1e-3)
+    assert hg[2] == pytest.approx(hr[2], rel=1e-3)
+    assert hg[2] < hg[1] < hg[0]
+    np.testing.assert_allclose(host(xg), xr, atol=2e-3 * 24)
+
+
 def test_barycenter_full_shape_one_step():
     from paper_2107_02010_amd.barycenter import barycenter_step
     maps = synth.density_maps(2, seed=3)
