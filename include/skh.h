@@ -302,6 +302,25 @@ int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const
                   float *grad_b, float *grad_x, float *grad_y);
 
 /*
+ * skh_gradients for the cost C(x, y) = |x - y|^P / P with P = cost_p in [1, 2]
+ * (Section 2, the cost and the parameter lines of the Algorithm: eps = blur^P,
+ * rho = reach^P), from the dual vectors of a solve with that cost
+ * (skh_params.cost_p = P).  Same arguments, layouts and ownership as
+ * skh_gradients; cost_p = 2 is skh_gradients itself.  dS/d alpha, dS/d beta
+ * take the same expression at that eps and rho;
+ *   grad_x S_i = sum_j pi_ij |x_i - y_j|^{P-2} (x_i - y_j)
+ *              - sum_k pi^aa_ik |x_i - x_k|^{P-2} (x_i - x_k)
+ * (envelope theorem on eq. (3), pi from eq. (4) with that cost; pairs at
+ * distance 0 contribute 0, the zero subgradient when P = 1), on a dense FP32
+ * path for P != 2.  Errors: those of skh_gradients, and SKH_EINVAL for cost_p
+ * outside [1, 2].
+ */
+int skh_gradients_p(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                    const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                    const float *p, const float *q, double blur, double reach, double cost_p,
+                    float *grad_a, float *grad_b, float *grad_x, float *grad_y);
+
+/*
  * Label transfer from a segmented atlas beta to a subject alpha (Section 3,
  * label transfer; eq. (7)): the cross dual vectors (f, g) of OT_{eps,rho}(alpha,
  * beta) from the symmetric loop, then soft labels

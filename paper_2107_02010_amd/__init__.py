@@ -426,25 +426,28 @@ def grad_x(x, a, y, b, f, g, p, blur: float) -> torch.Tensor:
     return out
 
 
-def gradients(x, a, y, b, pot, blur: float, reach=None, wrt=("a", "b", "x", "y")) -> dict:
+def gradients(x, a, y, b, pot, blur: float, reach=None, wrt=("a", "b", "x", "y"),
+              p: float = 2.0) -> dict:
     """Gradients of S with respect to the weights and positions of both measures from
     the dual vectors pot = {f, g, p, q} of a solve (Section 2: expressions of the four
     dual vectors).  dS/da_i = (rho + eps)(e^{-p_i/rho} - e^{-f_i/rho}) (f_i - p_i when
     balanced: then dS/da and dS/db share a free additive constant), dS/db likewise from
-    (g, q); dS/dx as grad_x, dS/dy with the roles exchanged.  wrt: which to compute."""
+    (g, q); dS/dx as grad_x, dS/dy with the roles exchanged.  wrt: which to compute.
+    p: exponent of the cost |x - y|^p / p the potentials were solved with (eps = blur^p,
+    rho = reach^p; dS/dx then weights each pair by |x_i - y_j|^{p-2})."""
     x, y = _as_points(x, "x"), _as_points(y, "y")
     n, m, d = x.shape[0], y.shape[0], x.shape[1]
     dev = x.device
     a, b = _as_vec(a, n, "a", dev), _as_vec(b, m, "b", dev)
     f, g = _as_vec(pot["f"], n, "f", dev), _as_vec(pot["g"], m, "g", dev)
-    p, q = _as_vec(pot["p"], n, "p", dev), _as_vec(pot["q"], m, "q", dev)
+    p_, q = _as_vec(pot["p"], n, "p", dev), _as_vec(pot["q"], m, "q", dev)
     shapes = {"a": (n,), "b": (m,), "x": (n, d), "y": (m, d)}
     out = {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in wrt}
     rr = 0.0 if reach is None else float(reach)
     ctx = _Ctx.get(dev)
-    rc = _lib.load().skh_gradients(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d, _ptr(f),
-                                   _ptr(g), _ptr(p), _ptr(q), float(blur), rr,
-                                   *(_ptr(out[k]) if k in out else None for k in "abxy"))
+    rc = _lib.load().skh_gradients_p(ctx, _ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, d, _ptr(f),
+                                     _ptr(g), _ptr(p_), _ptr(q), float(blur), rr, float(p),
+                                     *(_ptr(out[k]) if k in out else None for k in "abxy"))
     _lib.check(rc, ctx)
     return out
 
@@ -459,14 +462,11 @@ class SinkhornDivergence(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, a, y, b, kw):
-        if float(kw.get("p", 2.0)) != 2.0 and any(ctx.needs_input_grad[:4]):
-            # the gradient kernels implement the cost |x - y|^2 / 2 only; refuse rather
-            # than return the gradient of another problem
-            raise ValueError("gradients of S are implemented for the cost exponent p = 2 only")
         S, pot, st = sinkhorn_divergence(x, a, y, b, potentials=True, **kw)
         ctx.save_for_backward(x, a, y, b, pot["f"], pot["g"], pot["p"], pot["q"])
         ctx.blur = kw.get("blur", 0.05)
         ctx.reach = kw.get("reach", None)
+        ctx.cost_p = float(kw.get("p", 2.0))  # the backward uses the solve's cost
         return torch.tensor(S, dtype=torch.float64, device=x.device)
 
     @staticmethod
@@ -476,7 +476,8 @@ class SinkhornDivergence(torch.autograd.Function):
         res = {}
         if want:
             res = gradients(x.detach(), a.detach(), y.detach(), b.detach(),
-                            dict(f=f, g=g, p=p, q=q), ctx.blur, ctx.reach, wrt=tuple(want))
+                            dict(f=f, g=g, p=p, q=q), ctx.blur, ctx.reach, wrt=tuple(want),
+                            p=ctx.cost_p)
         src = {"x": x, "a": a, "y": y, "b": b}
         grads = [(res[k].to(torch.float64) * gS).to(src[k].dtype) if k in res else None
                  for k in "xayb"]

@@ -94,6 +94,9 @@ SIGNATURES = {
                             _c_vp, _c_d, _c_vp]),
     "skh_gradients": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp,
                                _c_vp, _c_vp, _c_vp, _c_d, _c_d, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "skh_gradients_p": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32, _c_vp,
+                                 _c_vp, _c_vp, _c_vp, _c_d, _c_d, _c_d, _c_vp, _c_vp, _c_vp,
+                                 _c_vp]),
     "skh_label_transfer": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_i32,
                                     _c_vp, _c_i32, _c_i32, ctypes.POINTER(SkhParams), _c_vp,
                                     _c_vp, ctypes.POINTER(SkhStats)]),

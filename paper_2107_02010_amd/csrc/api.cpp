@@ -1205,9 +1205,12 @@ struct PlanSpec {
     float *mass;          // n or NULL
 };
 
+// cost_p != 2: the cost |x - y|^p / p (eps is then blur^p); only the gradient sums
+// (V = NULL) exist for it.
 int run_plans(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d, double eps,
               int divide_by_a, const PlanSpec *specs, int nspec, float **Xp_out, int *kp_out,
-              hipStream_t s) {
+              hipStream_t s, double cost_p = 2.0) {
+    const bool pcost = cost_p != 2.0;
     const int kp = skh::packed_width(d);
     int Lmax = 1;
     for (int k = 0; k < nspec; ++k) Lmax = std::max(Lmax, specs[k].L);
@@ -1263,9 +1266,12 @@ int run_plans(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d
     }
     SKH_HIP(skh::launch_bbox_final(plo, phi, pmass, pbad, nb[0], nbt - nb[0], d, lohi, mass, bad, s));
     SKH_HIP(skh::launch_pack(x, nullptr, n, d, kp, lohi + 128, Xp, hnx, nullptr, s));
+    // the p-cost records carry no half-norm expansion terms
+    if (pcost) SKH_HIP(hipMemsetAsync(hnx, 0, (size_t)n * sizeof(float), s));
     for (int k = 0; k < nspec; ++k) {
         const PlanSpec &P = specs[k];
         SKH_HIP(skh::launch_pack(P.cols, P.cw, P.m, d, kp, lohi + 128, Cp[k], hnc[k], lwc[k], s));
+        if (pcost) SKH_HIP(hipMemsetAsync(hnc[k], 0, (size_t)P.m * sizeof(float), s));
         SKH_HIP(skh::launch_col_offsets(lwc[k], P.gpot, hnc[k], P.m, eps, uc[k], s));
         skh::PlanJob &J = batch.job[k];
         J.rows = Xp;
@@ -1274,7 +1280,10 @@ int run_plans(skh_ctx *ctx, const float *x, const float *a, int64_t n, int32_t d
         J.V = P.V;
         J.part = part[k];
     }
-    SKH_HIP(skh::launch_plan_weighted(batch, kp, lp, wgs, s));
+    if (pcost)
+        SKH_HIP(skh::launch_plan_pcost(batch, kp, (float)cost_p, wgs, s));
+    else
+        SKH_HIP(skh::launch_plan_weighted(batch, kp, lp, wgs, s));
     for (int k = 0; k < nspec; ++k) {
         const PlanSpec &P = specs[k];
         SKH_HIP(skh::launch_plan_finish(part[k], batch.job[k].n_chunks, (int)n, P.L, hnx, P.fpot,
@@ -1304,6 +1313,34 @@ int skh_plan_apply(skh_ctx *ctx, const float *x, const float *a, int64_t n, cons
     return run_plans(ctx, x, a, n, d, eps, divide_by_a, &sp, 1, nullptr, nullptr, ctx->stream);
 }
 
+namespace {
+
+// grad_x S from (f, g, p) for the cost |x - y|^cost_p / cost_p at eps = blur^cost_p
+int grad_x_impl(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                const float *p, double blur, double cost_p, float *grad) {
+    hipStream_t s = ctx->stream;
+    // value buffers in the loop workspace: P1, m1, P2, m2
+    float *buf;
+    const size_t words = (size_t)n * d * 2 + (size_t)n * 2;
+    {
+        int rc = ensure_ws(ctx, 1, words * sizeof(float) + 1024);
+        if (rc) return rc;
+        buf = static_cast<float *>(ctx->ws[1]);
+    }
+    float *P1 = buf, *P2 = P1 + (size_t)n * d, *m1 = P2 + (size_t)n * d, *m2 = m1 + n;
+    const double eps = std::pow(blur, cost_p);
+    PlanSpec sp[2] = {{y, b, m, f, g, nullptr, d, P1, m1}, {x, a, n, p, p, nullptr, d, P2, m2}};
+    float *Xp = nullptr;
+    int kp = 0;
+    int rc = run_plans(ctx, x, a, n, d, eps, 0, sp, 2, &Xp, &kp, s, cost_p);
+    if (rc) return rc;
+    SKH_HIP(skh::launch_grad_combine(Xp, (int)n, d, kp, P1, m1, P2, m2, grad, s));
+    return SKH_OK;
+}
+
+}  // namespace
+
 int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
                const float *b, int64_t m, int32_t d, const float *f, const float *g,
                const float *p, double blur, float *grad) {
@@ -1315,30 +1352,13 @@ int skh_grad_x(skh_ctx *ctx, const float *x, const float *a, int64_t n, const fl
     if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
     if (!(blur > 0.0) || !std::isfinite(blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
     DeviceGuard guard(ctx->device);
-    hipStream_t s = ctx->stream;
-    // value buffers in the loop workspace: P1, m1, P2, m2
-    float *buf;
-    const size_t words = (size_t)n * d * 2 + (size_t)n * 2;
-    {
-        int rc = ensure_ws(ctx, 1, words * sizeof(float) + 1024);
-        if (rc) return rc;
-        buf = static_cast<float *>(ctx->ws[1]);
-    }
-    float *P1 = buf, *P2 = P1 + (size_t)n * d, *m1 = P2 + (size_t)n * d, *m2 = m1 + n;
-    const double eps = blur * blur;
-    PlanSpec sp[2] = {{y, b, m, f, g, nullptr, d, P1, m1}, {x, a, n, p, p, nullptr, d, P2, m2}};
-    float *Xp = nullptr;
-    int kp = 0;
-    int rc = run_plans(ctx, x, a, n, d, eps, 0, sp, 2, &Xp, &kp, s);
-    if (rc) return rc;
-    SKH_HIP(skh::launch_grad_combine(Xp, (int)n, d, kp, P1, m1, P2, m2, grad, s));
-    return SKH_OK;
+    return grad_x_impl(ctx, x, a, n, y, b, m, d, f, g, p, blur, 2.0, grad);
 }
 
-int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
-                  const float *b, int64_t m, int32_t d, const float *f, const float *g,
-                  const float *p, const float *q, double blur, double reach, float *grad_a,
-                  float *grad_b, float *grad_x, float *grad_y) {
+int skh_gradients_p(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                    const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                    const float *p, const float *q, double blur, double reach, double cost_p,
+                    float *grad_a, float *grad_b, float *grad_x, float *grad_y) {
     if (!ctx) return SKH_EINVAL;
     if (!x || !a || !y || !b || !f || !g || !p || !q) return fail(ctx, SKH_EINVAL, "NULL argument");
     if (n < 1 || m < 1 || n > kMaxPoints || m > kMaxPoints)
@@ -1346,22 +1366,31 @@ int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const
     if (d < 1 || d > SKH_MAX_DIM) return fail(ctx, SKH_EINVAL, "d must be in [1, 63]");
     if (!(blur > 0.0) || !std::isfinite(blur)) return fail(ctx, SKH_EINVAL, "blur must be > 0");
     if (std::isnan(reach)) return fail(ctx, SKH_EINVAL, "reach is NaN");
+    if (!(cost_p >= 1.0 && cost_p <= 2.0)) return fail(ctx, SKH_EINVAL, "cost_p must be in [1, 2]");
     DeviceGuard guard(ctx->device);
     hipStream_t s = ctx->stream;
-    const double eps = blur * blur;
-    const double rho = (reach > 0.0 && std::isfinite(reach)) ? reach * reach : 0.0;
+    const double eps = std::pow(blur, cost_p);
+    const double rho = (reach > 0.0 && std::isfinite(reach)) ? std::pow(reach, cost_p) : 0.0;
     if (grad_a) SKH_HIP(skh::launch_grad_weights(f, p, n, eps, rho, grad_a, s));
     if (grad_b) SKH_HIP(skh::launch_grad_weights(g, q, m, eps, rho, grad_b, s));
     if (grad_x) {
-        const int rc = skh_grad_x(ctx, x, a, n, y, b, m, d, f, g, p, blur, grad_x);
+        const int rc = grad_x_impl(ctx, x, a, n, y, b, m, d, f, g, p, blur, cost_p, grad_x);
         if (rc) return rc;
     }
     if (grad_y) {
         // S is symmetric in (alpha, beta): the x formula with the roles exchanged
-        const int rc = skh_grad_x(ctx, y, b, m, x, a, n, d, g, f, q, blur, grad_y);
+        const int rc = grad_x_impl(ctx, y, b, m, x, a, n, d, g, f, q, blur, cost_p, grad_y);
         if (rc) return rc;
     }
     return SKH_OK;
+}
+
+int skh_gradients(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,
+                  const float *b, int64_t m, int32_t d, const float *f, const float *g,
+                  const float *p, const float *q, double blur, double reach, float *grad_a,
+                  float *grad_b, float *grad_x, float *grad_y) {
+    return skh_gradients_p(ctx, x, a, n, y, b, m, d, f, g, p, q, blur, reach, 2.0, grad_a, grad_b,
+                           grad_x, grad_y);
 }
 
 int skh_label_transfer(skh_ctx *ctx, const float *x, const float *a, int64_t n, const float *y,

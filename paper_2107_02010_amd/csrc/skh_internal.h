@@ -108,6 +108,9 @@ int plan_value_width(int L);  // 4..64, 0 if L > 64
 // workgroups (records per row: that many times L + 2 floats).
 constexpr int kMaxPlanTileChunks = 4;
 hipError_t launch_plan_weighted(const PlanBatch &b, int kp, int lp, int total_wgs, hipStream_t s);
+// gradient records for the cost |x - y|^p / p, p != 2 (dense jobs, V = NULL, L = d < kp;
+// packed half-norms zero): [M, sum 2^{s-M} w, sum 2^{s-M} w y], w = |x - y|^{p-2}
+hipError_t launch_plan_pcost(const PlanBatch &b, int kp, float pexp, int total_wgs, hipStream_t s);
 hipError_t launch_plan_finish(const float *part, int chunks, int n, int L, const float *hn,
                               const float *pot, const float *w, double eps, float *out,
                               float *mass, hipStream_t s);

@@ -96,15 +96,3 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
-
-
-def test_loss_refuses_gradients_for_other_cost_exponents():
-    # the gradient kernels implement p = 2: a p != 2 loss that needs a gradient must
-    # fail before any solve, not return the gradient of another problem
-    import torch
-
-    import paper_2107_02010_amd as skh
-    x = torch.zeros(4, 3, requires_grad=True)
-    a = torch.full((4,), 0.25)
-    with pytest.raises(ValueError, match="p = 2"):
-        skh.sinkhorn_loss(x, a, x.detach(), a, blur=0.1, p=1.5)
