@@ -407,13 +407,12 @@ def bench_pcost(args, skh, synth):
     st = agg["stats"]
     kern_s = agg["ms_softmin"] / agg["launches"] / 1e3
     ppl = agg["pairs"] / agg["launches"]
-    # VALU issue bound: per pair the formula needs d subtractions and d FMAs for |x - y|^2,
-    # the square root, the exponent FMA, the maximum, the subtraction of the level, the
-    # exponential and the sum (2 d + 6 lane operations, d = 3); without packed FP32 a
-    # SIMD issues 16 lanes per clock, transcendentals included: 256 CUs x 4 SIMDs x 16
-    # lanes x 2.4 GHz = 39.3e12 lane operations per second
-    ops = 2 * 3 + 6
-    peak = 256 * 4 * 16 * 2.4e9 / 1e12
+    # algorithmic ALU work per pair: d subtractions and d multiply-adds for |x - y|^2, the
+    # square root, the exponent FMA, the exponential and the sum (2 d + 2 lane operations
+    # plus two transcendentals at TRANS_SLOTS each, d = 3); the running maximum and the
+    # level subtraction are the kernel's own bookkeeping, not counted
+    ops = 2 * 3 + 2 + 2 * TRANS_SLOTS
+    peak = VALU_LANE_PEAK / 1e12
     ach = ops * ppl / kern_s / 1e12
     out = {"metric": "Gpair/s of the log-sum-exp softmin, cost |x - y| (full S_eps solve, "
                      f"{n} x {n} 3-D clouds)",
@@ -426,9 +425,129 @@ def bench_pcost(args, skh, synth):
                       "iterations": st["iters"]},
            "S": agg["S"], "softmin_kernel_gpair_s": round(ppl / kern_s / 1e9, 3),
            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 2),
-                        "unit": "Tops/s", "frac": round(ach / peak, 4), "traffic": None,
-                        "ops_per_pair": ops, "avg_launch_ms": round(kern_s * 1e3, 4),
+                        "unit": "Tslot/s", "frac": round(ach / peak, 4), "traffic": None,
+                        "slots_per_pair": ops, "avg_launch_ms": round(kern_s * 1e3, 4),
                         "kernel": "k_softmin_pcost<4, p = 1>"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# ALU ceiling of the VALU-bound kernels (3-D and p-cost softmins).  The issue-rate
+# probe (paper_2107_02010_amd/valu_probe, `--workload valu_probe`) measures a wave64
+# FP32 add at 2 clocks of a SIMD (32 lanes per clock: 256 CUs x 4 SIMDs x 32 lanes x
+# 2.4 GHz = 78.6e12 lane operations per second, the FP32 vector peak counted one
+# operation per lane) and v_exp_f32 at 4 such issue slots, not overlapping the adds.
+VALU_LANE_PEAK = 256 * 4 * 32 * 2.4e9
+TRANS_SLOTS = 4
+
+
+def bench_blobs(args, skh, synth):
+    """Full solve with the cost |x - y|^2 / 2 on 200k x 200k 3-D blob clouds (the 3-D
+    path of the small-point workloads): k_softmin_f32<4>, the 4-wide contraction on the
+    matrix cores, one exponential and one add per pair on the VALU."""
+    import torch
+    n = args.n
+    print(f"[bench] generating {n} x {n} 3-D blob clouds", file=sys.stderr, flush=True)
+    x, a, y, b = synth.blob_pair(n, seed=0)
+    X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+    kw = dict(blur=0.01, reach=None, scaling=0.9, potentials=True, timing=True,
+              precision="fp32")
+    agg = solve_steps(skh, X, A, Y, B, args.steps, args.warmup, "3-D p = 2", **kw)
+    st = agg["stats"]
+    kern_s = agg["ms_softmin"] / agg["launches"] / 1e3
+    ppl = agg["pairs"] / agg["launches"]
+    # algorithmic ALU work per pair: one exponential and one add (the 4-wide contraction
+    # runs on the matrix cores: 8 flop per pair, 19.7e12 pairs/s at the FP32 MFMA peak,
+    # above the ALU ceiling); issue slots of one lane operation each
+    slots = TRANS_SLOTS + 1
+    peak = VALU_LANE_PEAK / 1e12
+    ach = slots * ppl / kern_s / 1e12
+    out = {"metric": "Gpair/s of the log-sum-exp softmin (full S_eps solve, "
+                     f"{n} x {n} 3-D clouds)",
+           "value": round(agg["pairs"] / agg["dt"] / 1e9, 3), "unit": "Gpair/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(agg["dt"] / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3-D Gaussian blob clouds n=m={n}, cost |x-y|^2/2, "
+                                  "blur 0.01, balanced, scaling 0.9, dense",
+                      "iterations": st["iters"]},
+           "S": agg["S"], "softmin_kernel_gpair_s": round(ppl / kern_s / 1e9, 3),
+           "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 2),
+                        "unit": "Tslot/s", "frac": round(ach / peak, 4), "traffic": None,
+                        "slots_per_pair": slots, "avg_launch_ms": round(kern_s * 1e3, 4),
+                        "kernel": "k_softmin_f32<4>"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_warmstart_eval(args, skh, synth):
+    """What the learned warm start gains on fresh pairs (seeds disjoint from training):
+    per pair the cold BF16 multiscale solve, the zero-start ablation at the network's
+    schedule (same clustering, start scale and checks, starting values 0) and the
+    network's start, all converged to the same marginal error; five 1M x 1M pairs
+    (200 bundles) and eight 100k x 100k pairs (50-200 bundles)."""
+    import numpy as np
+    import torch
+    from paper_2107_02010_amd.warm_start import (DEFAULT_CHECKPOINT, WarmStartNet,
+                                                 sinkhorn_divergence_warm)
+    net = WarmStartNet.load(DEFAULT_CHECKPOINT, "cuda:0")
+    kw = dict(reach=20.0, tol=1e-4, check_every=1, max_iters=20000, multiscale=True,
+              timing=True)
+    rng = np.random.default_rng(900)
+    plan = [(1_000_000, 200, 900001 + k) for k in range(5)]
+    plan += [(100_000, int(rng.integers(50, 201)), 900101 + k) for k in range(8)]
+    rows = []
+    for n, nb, seed in plan:
+        print(f"[bench] pair n={n} bundles={nb} seed={seed}: generating", file=sys.stderr,
+              flush=True)
+        x, a, y, b = synth.fiber_pair(n, nb, seed=seed)
+        X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+        legs = {"cold": lambda: skh.sinkhorn_divergence(X, A, Y, B, blur=1.0, scaling=0.9,
+                                                        precision="bf16x3", potentials=True,
+                                                        **kw),
+                "zero_start": lambda: sinkhorn_divergence_warm(
+                    net, X, A, Y, B, 1.0, scaling=0.9, precision="bf16x3", start="zero", **kw),
+                "network": lambda: sinkhorn_divergence_warm(
+                    net, X, A, Y, B, 1.0, scaling=0.9, precision="bf16x3", **kw)}
+        row = {"n": n, "bundles": nb, "seed": seed}
+        for name, fn in legs.items():
+            fn()  # warm-up (workspace, clustering caches)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S, _, st = fn()
+            torch.cuda.synchronize()
+            row[name] = {"s": round(time.perf_counter() - t0, 4), "iters": st["iters"],
+                         "S": S, "fallback": st.get("warm_fallback", 0)}
+        print(f"[bench]   cold {row['cold']['iters']} it {row['cold']['s']:.3f} s | zero start "
+              f"{row['zero_start']['iters']} it {row['zero_start']['s']:.3f} s | network "
+              f"{row['network']['iters']} it {row['network']['s']:.3f} s", file=sys.stderr,
+              flush=True)
+        rows.append(row)
+        del X, A, Y, B
+        torch.cuda.empty_cache()
+
+    def summary(sel):
+        r = [q for q in rows if sel(q)]
+        return {"pairs": len(r),
+                "iters_cold": sum(q["cold"]["iters"] for q in r),
+                "iters_zero_start": sum(q["zero_start"]["iters"] for q in r),
+                "iters_network": sum(q["network"]["iters"] for q in r),
+                "s_cold": round(sum(q["cold"]["s"] for q in r), 4),
+                "s_zero_start": round(sum(q["zero_start"]["s"] for q in r), 4),
+                "s_network": round(sum(q["network"]["s"] for q in r), 4),
+                "max_S_rel_diff_network_vs_cold": max(
+                    abs(q["network"]["S"] - q["cold"]["S"]) / abs(q["cold"]["S"]) for q in r)}
+    out = {"metric": "learned warm start on fresh fibre pairs: iterations and time to S "
+                     "(cold, zero start at the network's schedule, network)",
+           "value": summary(lambda q: q["n"] == 1_000_000)["s_network"], "unit": "s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+           "config": {"workload": "fresh fibre pairs (seeds 900001-900005 at 1M x 1M, 200 "
+                                  "bundles; 900101-900108 at 100k x 100k, 50-200 bundles), "
+                                  "reach 20 mm, blur 1 mm, multiscale BF16, marginal error "
+                                  "1e-4 checked every iteration"},
+           "at_1m": summary(lambda q: q["n"] == 1_000_000),
+           "at_100k": summary(lambda q: q["n"] == 100_000), "pairs": rows}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -498,7 +617,8 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
     ap.add_argument("--workload", default="fibers1m",
                     choices=["fibers1m", "multiscale1m", "fibers200k", "grad200k", "labels200k",
-                             "labels250k", "pcost200k", "barycenter10"])
+                             "labels250k", "pcost200k", "blobs200k", "barycenter10",
+                             "warmstart_eval", "valu_probe"])
     ap.add_argument("--legs", default="chosen,plain,bf16_cold,zero_start,dense200k,cpu",
                     help="fibers1m: comma-separated legs to run (chosen, plain, bf16_cold, "
                          "zero_start, dense200k, cpu)")
@@ -539,6 +659,20 @@ def main() -> int:
         return bench_gradients(args, skh, synth)
     if args.workload in ("labels200k", "labels250k"):
         return bench_labels(args, skh, synth)
+    if args.workload == "valu_probe":
+        import subprocess
+        exe = os.path.join(ROOT, "paper_2107_02010_amd", "valu_probe")
+        if not os.path.exists(exe):
+            print("valu_probe is missing: build it with python -m paper_2107_02010_amd.build",
+                  file=sys.stderr)
+            return 1
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+        sys.stdout.write(r.stdout)
+        return r.returncode
+    if args.workload == "warmstart_eval":
+        return bench_warmstart_eval(args, skh, synth)
+    if args.workload == "blobs200k":
+        return bench_blobs(args, skh, synth)
     if args.workload == "pcost200k":
         return bench_pcost(args, skh, synth)
     if args.workload == "barycenter10":

@@ -17,6 +17,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libskh.so")
+# issue-rate probe behind the ALU ceilings of the bench's 3-D and p-cost lines
+PROBE_SRC = os.path.join(CSRC, "valu_probe.hip")
+PROBE = os.path.join(HERE, "valu_probe")
 
 SOURCES = ["softmin.hip", "softmin_bf16.hip", "softmin_pcost.hip", "plan.hip", "kmeans.hip", "multiscale.hip",
            "aux_kernels.hip", "warmstart.hip", "api.cpp", "ws_api.cpp"]
@@ -65,6 +68,11 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stderr}")
         os.replace(tmp_lib, LIB)
+        cmd = [cc, *HIP_FLAGS, "-x", "hip", PROBE_SRC, "-o", PROBE + ".tmp"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on valu_probe.hip:\n{r.stderr}")
+        os.replace(PROBE + ".tmp", PROBE)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
