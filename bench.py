@@ -480,6 +480,49 @@ def bench_blobs(args, skh, synth):
     return 0
 
 
+def bench_blobs2k(args, skh, synth):
+    """The small 3-D case: 2000 x 2000 Gaussian blobs, blur 0.01, scaling 0.5, balanced,
+    dense FP32, the Algorithm's schedule; latency-bound on the GPU (us per iteration),
+    with the FP64 oracle's full solve timed on the host at one thread and all cores."""
+    import torch
+
+    import oracle
+    x, a, y, b = synth.blob_pair(2000, seed=0)
+    X, A, Y, B = (torch.as_tensor(v).cuda() for v in (x, a, y, b))
+    kw = dict(blur=0.01, reach=None, scaling=0.5, potentials=True, timing=True,
+              precision="fp32")
+    agg = solve_steps(skh, X, A, Y, B, args.steps, args.warmup, "2k blobs", **kw)
+    st = agg["stats"]
+    t_gpu = agg["dt"] / args.steps
+    cpu = {}
+    threads_all = oracle.num_threads()
+    for label, k in (("one_core", 1), ("all_cores", threads_all)):
+        oracle.set_num_threads(k)
+        t0 = time.perf_counter()
+        Sr, r = oracle.sinkhorn_divergence(x, a, y, b, 0.01, None, scaling=0.5)
+        cpu[label] = {"s": round(time.perf_counter() - t0, 4), "threads": k, "S": Sr,
+                      "iters": r["iters"]}
+        print(f"[bench] oracle full solve ({label}, {k} threads): {cpu[label]['s']:.3f} s",
+              file=sys.stderr, flush=True)
+    oracle.set_num_threads(threads_all)
+    out = {"metric": "time to S_eps, 2000 x 2000 3-D blobs (the Algorithm's schedule)",
+           "value": round(t_gpu, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(t_gpu * 1e3, 4),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "3 Gaussian blobs per cloud, n=m=2000, blur 0.01, scaling "
+                                  "0.5, balanced, dense FP32", "iterations": st["iters"]},
+           "S": agg["S"], "us_per_iteration": round(t_gpu / st["iters"] * 1e6, 2),
+           "solve_gpair_s": round(agg["pairs"] / agg["dt"] / 1e9, 3),
+           "S_rel_diff_vs_oracle": abs(agg["S"] - cpu["one_core"]["S"]) / abs(cpu["one_core"]["S"]),
+           "cpu_baseline": {"value": cpu["all_cores"]["s"], "unit": "s",
+                            "cores": threads_all, "kind": "oracle", "cpu_model": cpu_model(),
+                            "sample": "the whole FP64 oracle solve (same inputs and schedule)",
+                            "one_core_s": cpu["one_core"]["s"]}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_warmstart_eval(args, skh, synth):
     """What the learned warm start gains on fresh pairs (seeds disjoint from training):
     per pair the cold BF16 multiscale solve, the zero-start ablation at the network's
@@ -618,7 +661,7 @@ def main() -> int:
     ap.add_argument("--workload", default="fibers1m",
                     choices=["fibers1m", "multiscale1m", "fibers200k", "grad200k", "labels200k",
                              "labels250k", "pcost200k", "blobs200k", "barycenter10",
-                             "warmstart_eval", "valu_probe"])
+                             "warmstart_eval", "valu_probe", "blobs2k"])
     ap.add_argument("--legs", default="chosen,plain,bf16_cold,zero_start,dense200k,cpu",
                     help="fibers1m: comma-separated legs to run (chosen, plain, bf16_cold, "
                          "zero_start, dense200k, cpu)")
@@ -659,6 +702,8 @@ def main() -> int:
         return bench_gradients(args, skh, synth)
     if args.workload in ("labels200k", "labels250k"):
         return bench_labels(args, skh, synth)
+    if args.workload == "blobs2k":
+        return bench_blobs2k(args, skh, synth)
     if args.workload == "valu_probe":
         import subprocess
         exe = os.path.join(ROOT, "paper_2107_02010_amd", "valu_probe")

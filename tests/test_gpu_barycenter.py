@@ -75,6 +75,71 @@ def test_barycenter_full_shape_one_step():
     np.testing.assert_allclose(g.astype(np.float64).mean(0), ybar, atol=0.5)
 
 
+def test_barycenter_full_shape_sampled_rows_against_oracle():
+    # full C5 shape (128^3 maps, 200k support), one step with the cross loops iterated to
+    # a marginal error of 1e-4: sampled rows of f_k and columns of g_k sit at the
+    # balanced fixed point (the oracle's softmin over every point of the other side),
+    # S_k is eq. (6) of the returned vectors, and the sampled rows of the step equal the
+    # oracle's plan sums on the same FP32 potentials (plan apply is row-separable)
+    from paper_2107_02010_amd.barycenter import barycenter_step
+    maps = synth.density_maps(2, seed=3)
+    x0, a = synth.barycenter_support(maps, 200_000, seed=4)
+    ym = [(cuda(c), cuda(w)) for c, w in maps]
+    note("barycenter 128^3 maps, 200k support, converged step vs oracle rows")
+    x1, S, pots = barycenter_step(cuda(x0), cuda(a), ym, blur=1.0, scaling=0.9, tol=1e-4,
+                                  max_iters=5000)
+    x1 = host(x1)
+    rng = np.random.default_rng(17)
+    rows = rng.choice(len(x0), 24, replace=False)
+    eps = 1.0
+    x64 = x0.astype(np.float64)
+    # FP32 rounding of one exponent (coordinates centred on the joint bounding box of a
+    # 128^3 grid, |x~|, |y~| <= r): the softmin bound 8 u (sqrt(d + 2) (|x~||y~| + |g - |y~|^2/2|)
+    # + |x~|^2/2) / eps is at most 8 u 4 r^2 / eps here, u = 2^-24; every weight of the
+    # GPU's plan carries up to that relative error
+    pts = np.vstack([x64] + [c.astype(np.float64) for c, _ in maps])
+    mid = 0.5 * (pts.max(0) + pts.min(0))
+    r = np.linalg.norm(pts - mid, axis=1).max()
+    e32 = 8 * 2.0 ** -24 * 4.0 * r * r / eps
+    p = host(pots[0]["p"]).astype(np.float64)
+    grad = np.zeros((len(rows), 3))
+    spread = np.zeros(len(rows))
+    Ss = []
+    for k, (c, w) in enumerate(maps):
+        f, g = host(pots[k]["f"]).astype(np.float64), host(pots[k]["g"]).astype(np.float64)
+        q = host(pots[k]["q"]).astype(np.float64)
+        cols = rng.choice(len(c), 24, replace=False)
+        ft = oracle.softmin(x0[rows], c, w, g, eps)
+        gt = oracle.softmin(c[cols], x0, a, f, eps)
+        dev = np.abs(np.expm1((np.concatenate([f[rows], g[cols]])
+                               - np.concatenate([ft, gt])) / eps))
+        print(f"map {k}: fixed-point deviation mean {dev.mean():.2e} max {dev.max():.2e} "
+              f"(FP32 exponent bound {e32:.2e})")
+        # the stopping rule (relative L1 marginal error 1e-4) plus the FP32 exponent error
+        assert dev.max() <= 1e-3 + e32
+        Ss.append(oracle.divergence(a, w, f, g, p, q, 1.0))
+        # grad_i = (m1 x_i - P1_i) - (m2 x_i - P2_i) from the oracle's plan sums, and the
+        # plan's second moment sum_j pi_ij |x_i - y_j|^2 = m1 |x_i|^2 - 2 x_i.P1 + sum pi |y|^2
+        c64 = c.astype(np.float64)
+        c1 = oracle.plan_apply(x0[rows], a[rows], c, w, f[rows], g, eps,
+                               np.hstack([c64, np.ones((len(c), 1)), (c64 ** 2).sum(1, keepdims=True)]))
+        c2 = oracle.plan_apply(x0[rows], a[rows], x0, a, p[rows], p, eps,
+                               np.hstack([x64, np.ones((len(x0), 1)), (x64 ** 2).sum(1, keepdims=True)]))
+        xr = x64[rows]
+        grad += (c1[:, 3:4] * xr - c1[:, :3]) - (c2[:, 3:4] * xr - c2[:, :3])
+        for cc in (c1, c2):
+            m2nd = cc[:, 3] * (xr ** 2).sum(1) - 2 * (xr * cc[:, :3]).sum(1) + cc[:, 4]
+            spread += np.sqrt(np.maximum(m2nd, 0.0) * cc[:, 3]) / a[rows]
+    assert S == pytest.approx(np.mean(Ss), rel=1e-5)
+    step = x64[rows] - (grad / len(maps)) / a[rows, None].astype(np.float64)
+    # a relative error e32 in each weight moves grad_i / a_i by at most e32 times the
+    # plans' mean transport distance (Cauchy-Schwarz on the second moment), per map
+    tol = 2.0 * e32 * spread / len(maps) + 1e-3
+    err = np.abs(x1[rows] - step).max(1)
+    print("largest step difference at the sampled rows", err.max(), "bound", tol.min(), tol.max())
+    assert np.all(err <= tol)
+
+
 def test_multiscale_step_matches_dense_step():
     # each map's cross loop on the coarse-to-fine scheme (cold start, p and q fixed)
     # against the dense cross loops, both iterated at blur to a marginal error of 1e-5:
